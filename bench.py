@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of the motion-compensation hot path on one MI355X.
+
+A step is one iteration of gradient-based motion estimation over a 256^3 volume
+(1 mm voxels) reconstructed from 496 views (200-degree short scan, 620x480
+detector at 0.616 mm, 785/1200 mm): cubic B-spline motion model -> Eq. 1
+composition and brick set-up -> FDK backprojection (Eq. 3) -> entropy + TV
+loss and its seed -> Jacobian-vector product (Eq. 4-5) -> reduction and chain
+to the rigid parameters (Eq. 2) -> B-spline adjoint -> Adam step. Inputs are
+seeded synthetic data (head-like ellipsoid phantom, analytic projections,
+FDK pre-filter), resident in HBM before timing starts.
+
+Prints one JSON line. ``value`` is voxel-view updates per second of the whole
+step (GUPS = K * N_p / t_step / 1e9). The roofline object is for the dominant
+kernel (the VJP), timed with HIP events on the stream it runs on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GUPS (voxel·view/s) fwd+Jacobian 256³×496 views; p50/p99 solve latency"
+# algorithmic FP32 flops per voxel-view update (FMA = 2), FDK weighting, paper gradient
+FLOPS_FWD = 23
+FLOPS_VJP = 66
+PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (published)
+PEAK_HBM_GBS = 8000.0
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    f = int(k)
+    c = min(f + 1, len(xs) - 1)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def cpu_baseline(case, n_views_sample):
+    """The FP64 oracle (as it stands) on a bounded sample of the same workload: forward and
+    VJP over the whole grid for the first n_views_sample views."""
+    import dataclasses
+
+    import numpy as np
+
+    import oracle
+
+    scan = dataclasses.replace(case.scan, n_views=n_views_sample)
+    geo = oracle.geom_from(scan, case.grid, "fdk", "paper")
+    Phat, dPhat = oracle.compose(case.theta_true[:n_views_sample], case.P[:n_views_sample])
+    proj = np.ascontiguousarray(case.proj[:n_views_sample])
+    rng = np.random.default_rng(99)
+    delta = rng.standard_normal(case.grid.shape)
+    t0 = time.perf_counter()
+    oracle.backproject(geo, proj, Phat)
+    t1 = time.perf_counter()
+    G = oracle.vjp(geo, proj, Phat, delta)
+    oracle.chain(G, dPhat)
+    t2 = time.perf_counter()
+    updates = case.grid.n_voxels * n_views_sample
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": updates / (t2 - t0) / 1e9, "unit": "GUPS", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle forward (%.1f s) + VJP with chain (%.1f s) over the full %s grid for %d of %d views"
+                      % (t1 - t0, t2 - t1, "x".join(map(str, case.grid.shape)), n_views_sample, case.scan.n_views)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="head256")
+    ap.add_argument("--lr", type=float, default=0.05)
+    ap.add_argument("--cpu-views", type=int, default=16, help="views of the oracle's bounded CPU sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d, WORLD_SIZE %d)"
+              % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2401_09283_amd import gmc
+    from paper_2401_09283_amd.autograd import Backprojector
+    from synth import CONFIGS, make_case
+
+    cfg = CONFIGS[args.config]
+    t_gen = time.perf_counter()
+    case = make_case(args.config)
+    t_gen = time.perf_counter() - t_gen
+    print("bench: generated %s inputs in %.1f s" % (args.config, t_gen), file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bp = Backprojector.from_case(case, device=dev)
+    plan, ws = bp.plan, bp.workspace
+    n, nn = cfg.n_views, cfg.n_nodes
+    proj = torch.from_numpy(case.proj).to(dev)
+    P = bp.P
+    coeffs = torch.zeros((6, nn), dtype=torch.float64, device=dev)
+    m_ = torch.zeros_like(coeffs)
+    v_ = torch.zeros_like(coeffs)
+    gc = torch.empty_like(coeffs)
+    theta = torch.empty((n, 6), dtype=torch.float64, device=dev)
+    gtheta = torch.empty((n, 6), dtype=torch.float64, device=dev)
+    vol = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
+    gvol = torch.empty_like(vol)
+    loss = torch.empty(5, dtype=torch.float64, device=dev)
+    lo, hi, eps = -0.01, 0.06, 1e-5
+
+    # lambda: equal gradient norms of the entropy and TV terms at theta = 0 (one sync, untimed)
+    gmc.gmc_bspline_theta(n, nn, coeffs, theta)
+    gmc.gmc_prepare(plan, P, theta, 1, ws)
+    gmc.gmc_bp_forward(plan, proj, vol, ws)
+    gmc.gmc_loss_entropy_tv(plan, vol, 0.0, lo, hi, eps, gvol, loss, ws)
+    l0 = loss.cpu().numpy()
+    lam = float(np.sqrt(l0[3] / max(l0[4], 1e-300)))
+
+    ev = {k: [] for k in ("f0", "f1", "v0", "v1", "s0", "s1")}
+
+    def step(it, timed):
+        e = {k: torch.cuda.Event(enable_timing=True) for k in ev} if timed else None
+        if timed:
+            e["s0"].record()
+        gmc.gmc_bspline_theta(n, nn, coeffs, theta)
+        gmc.gmc_prepare(plan, P, theta, 1, ws)
+        if timed:
+            e["f0"].record()
+        gmc.gmc_bp_forward(plan, proj, vol, ws)
+        if timed:
+            e["f1"].record()
+        gmc.gmc_loss_entropy_tv(plan, vol, lam, lo, hi, eps, gvol, loss, ws)
+        if timed:
+            e["v0"].record()
+        gmc.gmc_bp_vjp(plan, proj, gvol, ws)
+        if timed:
+            e["v1"].record()
+        gmc.gmc_bp_vjp_finish(plan, gtheta, None, ws)
+        gmc.gmc_bspline_grad(n, nn, gtheta, gc)
+        gmc.gmc_adam_step(coeffs, gc, m_, v_, it + 1, args.lr)
+        if timed:
+            e["s1"].record()
+            for k in ev:
+                ev[k].append(e[k])
+
+    for it in range(args.warmup):
+        step(it, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(args.warmup, args.warmup + args.steps):
+        step(it, True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bp.check()
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    t_fwd = [a.elapsed_time(b) for a, b in zip(ev["f0"], ev["f1"])]
+    t_vjp = [a.elapsed_time(b) for a, b in zip(ev["v0"], ev["v1"])]
+    t_stp = [a.elapsed_time(b) for a, b in zip(ev["s0"], ev["s1"])]
+    upd = cfg.updates
+    fwd_ms, vjp_ms = float(np.mean(t_fwd)), float(np.mean(t_vjp))
+    achieved = FLOPS_VJP * upd / (vjp_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": upd / (ms_step * 1e-3) / 1e9,
+        "unit": "GUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %d^3 @ %g mm, %d views over %g deg, %dx%d detector @ %g mm; one motion-estimation "
+                        "iteration (B-spline, compose, FDK backprojection, entropy+TV loss, VJP, chain, Adam)"
+                        % (cfg.name, cfg.n, cfg.voxel_mm, cfg.n_views, cfg.arc_deg, cfg.det_w, cfg.det_h,
+                           cfg.pitch_mm),
+            "voxel_view_updates": upd,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_bp VJP (Eq. 4-5)",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None,
+            "flops_per_update": FLOPS_VJP,
+            "avg_launch_ms": vjp_ms,
+        },
+        "kernels": {
+            "bp_forward_ms": fwd_ms,
+            "bp_vjp_ms": vjp_ms,
+            "gups_forward": upd / (fwd_ms * 1e-3) / 1e9,
+            "gups_vjp": upd / (vjp_ms * 1e-3) / 1e9,
+            "gups_fwd_plus_jacobian": upd / ((fwd_ms + vjp_ms) * 1e-3) / 1e9,
+            "forward_tflops": FLOPS_FWD * upd / (fwd_ms * 1e-3) / 1e12,
+        },
+        "latency_ms": {"step_p50": percentile(t_stp, 50), "step_p99": percentile(t_stp, 99)},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on %d views" % args.cpu_views, file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_views)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,87 @@
+// Internal declarations shared by the HIP translation units of libgmc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gmc.h"
+
+namespace gmc {
+
+// Voxel bricks are BXY x BXY columns of BZ voxels; one workgroup of BXY*BXY threads owns
+// a brick and each thread owns one column (a run of BZ voxels along z).
+constexpr int BXY = 16;
+constexpr int THREADS = BXY * BXY;
+
+// One per (view, brick), 64 bytes, read with scalar loads by the backprojection kernels.
+// The local matrix m maps brick-local coordinates q (mm, relative to the centre of the
+// brick's first voxel) to (u'', v'', w) with u'' = u - ou*w and v'' = v - ov*w, so
+// u''/w is the detector column relative to the tile origin ou.
+struct BrickDesc {
+    float m[12];
+    int32_t ou, ov;   // detector column / row of tile index 0
+    int32_t tw, th;   // tile extent; tw == 0: nothing to sample (skip); tw < 0: sample from global memory
+};
+static_assert(sizeof(BrickDesc) == 64, "descriptor must be 64 bytes");
+
+// Per-(view, brick) partial of the VJP: 12 entries of G in the brick-local frame, then
+// the tile origin (ou, ov) as int bits, then 2 unused slots.
+constexpr int PART_STRIDE = 16;
+
+// Tile configurations (pitch TP floats, TH rows per plane) compiled into the kernels.
+struct TileCfg {
+    int tp, th;
+};
+constexpr TileCfg TILE_CFGS[] = {{40, 40}, {80, 72}, {128, 96}};
+constexpr int N_TILE_CFGS = 3;
+
+constexpr int LOSS_BLOCKS = 1024;   // blocks of the reduction kernels of the losses
+constexpr int HIST_BINS = 64;
+
+}  // namespace gmc
+
+struct gmc_plan {
+    gmc_geometry g;
+    int bz;                      // brick depth (voxels along z)
+    int nbx, nby, nbz, n_bricks;
+    int tile_cfg;                // index into TILE_CFGS
+    // workspace layout (byte offsets)
+    size_t off_phat, off_dphat, off_desc, off_part, off_G, off_status, off_loss, off_hist, ws_bytes;
+};
+
+namespace gmc {
+
+struct BpArgs {
+    const float* proj;
+    const BrickDesc* desc;
+    float* vol;          // forward output
+    const float* gvol;   // VJP seed
+    float* part;         // VJP partials [view][brick][PART_STRIDE]
+    int nx, ny, nz, W, H, n_views, nbx, nby, nbz, n_bricks, per_xcd;
+    float dx, dy, dz;
+    long long plane;     // W*H
+};
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_compose(const double* theta, const double* P, double* Phat, double* dPhat, int n_views,
+                          hipStream_t s);
+hipError_t launch_setup(const gmc_plan* p, const double* Phat, BrickDesc* desc, int* status, hipStream_t s);
+hipError_t launch_bp(const gmc_plan* p, const BpArgs& a, bool vjp, hipStream_t s);
+hipError_t launch_reduce_chain(const gmc_plan* p, const float* part, const double* dPhat, double* G,
+                               double* grad_theta, double* grad_P, hipStream_t s);
+hipError_t launch_debug_project(const gmc_plan* p, const BrickDesc* desc, long long n, const int64_t* voxel,
+                                const int32_t* view, int32_t* cell, float* frac, hipStream_t s);
+hipError_t launch_loss_sumsq(const gmc_plan* p, const float* vol, float* grad, double* scratch, double* loss,
+                             hipStream_t s);
+hipError_t launch_loss_entropy_tv(const gmc_plan* p, const float* vol, double lambda, double lo, double hi,
+                                  double eps, float* grad, double* scratch, double* hist, double* loss,
+                                  hipStream_t s);
+hipError_t launch_bspline_theta(int n_views, int n_nodes, const double* coeffs, double* theta, hipStream_t s);
+hipError_t launch_bspline_grad(int n_views, int n_nodes, const double* grad_theta, double* grad_coeffs,
+                               hipStream_t s);
+hipError_t launch_adam(long long n, double* x, const double* g, double* m, double* v, int t, double lr,
+                       double b1, double b2, double eps, hipStream_t s);
+hipError_t launch_gd(long long n, double* x, const double* g, double step, hipStream_t s);
+
+}  // namespace gmc

@@ -80,19 +80,24 @@ def parker_weights(g: ScanGeometry) -> np.ndarray:
 
 def fdk_filter(g: ScanGeometry, p: np.ndarray) -> np.ndarray:
     """Filtered projections d [n_views][det_h][det_w] (float64) from line integrals p."""
+    import torch
+
     tau = g.pitch_mm * g.dso_mm / g.dsd_mm
     W = g.det_w
     h = ramlak_kernel(W - 1, tau)           # covers every lag of a row
     nfft = 1 << int(math.ceil(math.log2(3 * W - 2)))
-    Hf = np.fft.rfft(h, nfft)
-    cw = cosine_weights(g)
-    pw = parker_weights(g)
+    Hf = torch.fft.rfft(torch.from_numpy(h), nfft)
     wscale = g.dbeta if not g.full_scan else g.dbeta / 2.0
-    out = np.empty_like(p)
-    for j in range(g.n_views):
-        x = p[j] * cw * pw[j][None, :]
-        X = np.fft.rfft(x, nfft, axis=1)
-        y = np.fft.irfft(X * Hf[None, :], nfft, axis=1)
+    cw = torch.from_numpy(cosine_weights(g) * (wscale * tau))
+    pw = torch.from_numpy(parker_weights(g))
+    pt = torch.from_numpy(np.ascontiguousarray(p, dtype=np.float64))
+    out = np.empty(p.shape, dtype=np.float64)
+    ot = torch.from_numpy(out)
+    chunk = max(1, (1 << 25) // (g.det_h * nfft))
+    for j0 in range(0, g.n_views, chunk):
+        j1 = min(g.n_views, j0 + chunk)
+        x = pt[j0:j1] * cw[None] * pw[j0:j1, None, :]
+        y = torch.fft.irfft(torch.fft.rfft(x, nfft, dim=2) * Hf, nfft, dim=2)
         # linear convolution: output index n of x*h lives at n + (W-1)
-        out[j] = wscale * tau * y[:, W - 1:2 * W - 1]
+        ot[j0:j1] = y[:, :, W - 1:2 * W - 1]
     return out

@@ -14,7 +14,9 @@ simulated this way is reconstructed sharply by P_j T_j.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import ctypes
 import os
+import subprocess
 
 import numpy as np
 
@@ -87,9 +89,13 @@ def _project_view(g: ScanGeometry, ph: Phantom, j: int, Tinv: np.ndarray, S, e_u
     return out
 
 
-def line_integrals(g: ScanGeometry, ph: Phantom, theta=None, cull: bool = True,
-                   workers: int | None = None) -> np.ndarray:
-    """Line integrals [n_views][det_h][det_w] (float64) of the phantom moved by T(theta_j)."""
+def line_integrals_numpy(g: ScanGeometry, ph: Phantom, theta=None, cull: bool = True,
+                        workers: int = 1) -> np.ndarray:
+    """NumPy version of ``line_integrals`` (slow; kept as the reference of the C version).
+
+    Single-threaded by default: concurrent small matrix products from several Python
+    threads were seen to corrupt results with the bundled BLAS.
+    """
     if theta is None:
         theta = np.zeros((g.n_views, 6))
     T = rigid_transform(theta)
@@ -97,8 +103,6 @@ def line_integrals(g: ScanGeometry, ph: Phantom, theta=None, cull: bool = True,
     S = source_positions(g)
     e_u, e_v, e_w = detector_frames(g)
     out = np.empty((g.n_views, g.det_h, g.det_w))
-    if workers is None:
-        workers = min(16, os.cpu_count() or 1)
 
     def work(j):
         out[j] = _project_view(g, ph, j, Tinv[j], S, e_u, e_v, e_w, cull)
@@ -109,4 +113,49 @@ def line_integrals(g: ScanGeometry, ph: Phantom, theta=None, cull: bool = True,
     else:
         with cf.ThreadPoolExecutor(workers) as ex:
             list(ex.map(work, range(g.n_views)))
+    return out
+
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_CSRC = os.path.join(_HERE, "_project.c")
+_CLIB = os.path.join(_HERE, "libsynth.so")
+_clib = None
+
+
+def build_c(force: bool = False) -> str:
+    if force or not os.path.exists(_CLIB) or os.path.getmtime(_CLIB) < os.path.getmtime(_CSRC):
+        tmp = _CLIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _CSRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _CLIB)
+    return _CLIB
+
+
+def _c():
+    global _clib
+    if _clib is None:
+        L = ctypes.CDLL(build_c())
+        vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.synth_line_integrals.argtypes = [i32, i32, i32, f64, f64, f64, vp, vp, i32, vp, vp, vp, vp, vp]
+        L.synth_line_integrals.restype = None
+        _clib = L
+    return _clib
+
+
+def line_integrals(g: ScanGeometry, ph: Phantom, theta=None, cull: bool = True,
+                   workers: int | None = None) -> np.ndarray:
+    """Line integrals [n_views][det_h][det_w] (float64) of the phantom moved by T(theta_j)."""
+    if not cull:
+        return line_integrals_numpy(g, ph, theta, cull=False)
+    if theta is None:
+        theta = np.zeros((g.n_views, 6))
+    Tinv = np.ascontiguousarray(np.linalg.inv(rigid_transform(theta)))
+    betas = np.ascontiguousarray(g.betas)
+    cen = np.ascontiguousarray(ph.centres, dtype=np.float64)
+    ax = np.ascontiguousarray(ph.axes, dtype=np.float64)
+    rot = np.ascontiguousarray(ph.rot, dtype=np.float64)
+    mu = np.ascontiguousarray(ph.mu, dtype=np.float64)
+    out = np.empty((g.n_views, g.det_h, g.det_w))
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    _c().synth_line_integrals(g.n_views, g.det_w, g.det_h, g.pitch_mm, g.dso_mm, g.dsd_mm, p(betas), p(Tinv),
+                              ph.n, p(cen), p(ax), p(rot), p(mu), p(out))
     return out

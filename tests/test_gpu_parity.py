@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on identical inputs.
+
+Bars: volumes max|I - I_ref| / max|I_ref| <= 1e-4; gradients per parameter type
+max_j |g - ref| / max_j |ref| <= 1e-3 (tests/parity.py). Integer work (detector
+cell indices) is compared exactly outside the FP32 rounding band. Every case
+also runs the global-memory sampler (tiles forced out of LDS), which must agree
+bit for bit with the LDS path.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from parity import GRAD_TOL, VOL_TOL, case, grad_err, mat_err, vol_err
+from synth.geometry import ScanGeometry, VolumeGrid, projection_matrices
+
+pytestmark = pytest.mark.gpu
+
+from paper_2401_09283_amd import gmc  # noqa: E402
+from paper_2401_09283_amd.autograd import Backprojector, backproject  # noqa: E402
+
+DEV = "cuda"
+
+
+def _t(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype).contiguous()
+
+
+class Setup:
+    def __init__(self, scan, grid, P, theta, proj, weighting="fdk", grad_mode="paper", flags=0):
+        self.scan, self.grid = scan, grid
+        self.P, self.theta, self.proj = P, theta, proj
+        self.bp = Backprojector(scan.n_views, scan.det_w, scan.det_h, grid.shape, grid.voxel_mm, grid.origin_mm, P,
+                                weighting, grad_mode, flags)
+        self.proj_d = _t(proj, torch.float32)
+        self.theta_d = _t(theta, torch.float64)
+        self.geo = oracle.geom_from(scan, grid, weighting, grad_mode)
+        self.Phat, self.dPhat = oracle.compose(theta, P)
+
+    def fwd(self):
+        v = self.bp.forward(self.proj_d, self.theta_d)
+        return v.cpu().numpy()
+
+    def vjp(self, delta):
+        gP = torch.empty((self.scan.n_views, 3, 4), dtype=torch.float64, device=DEV)
+        g = self.bp.vjp(self.proj_d, self.theta_d, _t(delta, torch.float32), grad_P=gP)
+        return g.cpu().numpy(), gP.cpu().numpy()
+
+
+def _report(name, **kv):
+    print("[%s] " % name + " ".join("%s=%s" % (k, v) for k, v in kv.items()), flush=True)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return case("tiny")
+
+
+def test_compose_matches_oracle(tiny):
+    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj)
+    n = tiny.scan.n_views
+    Phat = torch.empty((n, 3, 4), dtype=torch.float64, device=DEV)
+    dPhat = torch.empty((n, 6, 3, 4), dtype=torch.float64, device=DEV)
+    gmc.gmc_compose(s.bp.plan, s.theta_d, s.bp.P, Phat, dPhat)
+    assert np.allclose(Phat.cpu().numpy(), s.Phat, rtol=1e-14, atol=1e-12)
+    assert np.allclose(dPhat.cpu().numpy(), s.dPhat, rtol=1e-13, atol=1e-12)
+
+
+@pytest.mark.parametrize("weighting", ["fdk", "paper"])
+@pytest.mark.parametrize("flags", [0, gmc.FLAG_FORCE_GLOBAL])
+def test_forward_tiny(tiny, weighting, flags):
+    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj, weighting, flags=flags)
+    got = s.fwd()
+    ref = oracle.backproject(s.geo, tiny.proj, s.Phat)
+    e = vol_err(got, ref)
+    _report("forward tiny", weighting=weighting, flags=flags, err=e)
+    assert e <= VOL_TOL
+    s.bp.check()
+
+
+@pytest.mark.parametrize("weighting", ["fdk", "paper"])
+@pytest.mark.parametrize("grad_mode", ["paper", "exact"])
+def test_vjp_tiny_random_seed(tiny, weighting, grad_mode):
+    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj, weighting, grad_mode)
+    delta = np.random.default_rng(99).standard_normal(tiny.grid.shape).astype(np.float32)
+    g, gP = s.vjp(delta)
+    G = oracle.vjp(s.geo, tiny.proj, s.Phat, delta)
+    ref = oracle.chain(G, s.dPhat)
+    e = grad_err(g, ref)
+    _report("vjp tiny", weighting=weighting, grad=grad_mode, err=np.array2string(e, precision=2), errP=mat_err(gP, G))
+    assert np.all(e <= GRAD_TOL)
+    assert mat_err(gP, G) <= GRAD_TOL
+
+
+def test_vjp_tiny_loss_seed_and_global_path_bitwise(tiny):
+    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj)
+    sg = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj, flags=gmc.FLAG_FORCE_GLOBAL)
+    vol = s.fwd()
+    from oracle import losses
+
+    _, delta = losses.sumsq_grad(vol)
+    delta = delta.astype(np.float32)
+    g, gP = s.vjp(delta)
+    g2, gP2 = sg.vjp(delta)
+    G = oracle.vjp(s.geo, tiny.proj, s.Phat, delta)
+    e = grad_err(g, oracle.chain(G, s.dPhat))
+    _report("vjp tiny loss seed", err=np.array2string(e, precision=2))
+    assert np.all(e <= GRAD_TOL)
+    assert np.array_equal(g, g2) and np.array_equal(gP, gP2)
+    assert np.array_equal(vol, sg.fwd())
+
+
+def test_determinism(tiny):
+    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj)
+    delta = np.random.default_rng(5).standard_normal(tiny.grid.shape).astype(np.float32)
+    a, b = s.fwd(), s.fwd()
+    assert np.array_equal(a, b)
+    g1, _ = s.vjp(delta)
+    g2, _ = s.vjp(delta)
+    assert np.array_equal(g1, g2)
+
+
+def test_ragged_grid_and_detector_edges():
+    """Grid not a multiple of the brick, volume wider than the field of view (taps leave the
+    detector), odd detector, strong motion."""
+    scan = ScanGeometry(n_views=37, det_w=75, det_h=41, pitch_mm=1.3)
+    grid = VolumeGrid(37, 29, 21, (1.7, 1.9, 1.6))
+    rng = np.random.default_rng(17)
+    P = projection_matrices(scan)
+    th = np.concatenate([rng.uniform(-6, 6, (scan.n_views, 3)), rng.uniform(-0.1, 0.1, (scan.n_views, 3))], 1)
+    proj = rng.standard_normal((scan.n_views, scan.det_h, scan.det_w)).astype(np.float32)
+    delta = rng.standard_normal(grid.shape).astype(np.float32)
+    for weighting in ("fdk", "paper"):
+        for flags in (0, gmc.FLAG_FORCE_GLOBAL):
+            s = Setup(scan, grid, P, th, proj, weighting, flags=flags)
+            ev = vol_err(s.fwd(), oracle.backproject(s.geo, proj, s.Phat))
+            g, _ = s.vjp(delta)
+            eg = grad_err(g, oracle.chain(oracle.vjp(s.geo, proj, s.Phat, delta), s.dPhat))
+            _report("ragged", weighting=weighting, flags=flags, vol=ev, grad=np.array2string(eg, precision=2))
+            assert ev <= VOL_TOL
+            assert np.all(eg <= GRAD_TOL)
+
+
+def test_single_voxel_and_single_view():
+    scan = ScanGeometry(n_views=1, det_w=9, det_h=7, pitch_mm=1.0)
+    grid = VolumeGrid(1, 1, 1, (1.0, 1.0, 1.0))
+    P = projection_matrices(scan)
+    proj = np.tile(np.arange(9, dtype=np.float32)[None, None, :], (1, 7, 1))
+    s = Setup(scan, grid, P, np.zeros((1, 6)), proj, "paper")
+    assert s.fwd().ravel()[0] == pytest.approx(4.0, abs=1e-5)
+    g, gP = s.vjp(np.ones((1, 1, 1), dtype=np.float32))
+    assert np.allclose(gP[0], [[0, 0, 0, 1], [0, 0, 0, 0], [0, 0, 0, -4]], atol=1e-5)
+
+
+def test_geometry_index_parity(tiny):
+    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj)
+    s.fwd()
+    rng = np.random.default_rng(23)
+    n = 100000
+    vox = rng.integers(0, tiny.grid.n_voxels, n)
+    view = rng.integers(0, tiny.scan.n_views, n).astype(np.int32)
+    cell = torch.empty((n, 2), dtype=torch.int32, device=DEV)
+    frac = torch.empty((n, 2), dtype=torch.float32, device=DEV)
+    gmc.gmc_debug_project(s.bp.plan, _t(vox, torch.int64), _t(view, torch.int32), cell, frac, s.bp.workspace)
+    cell = cell.cpu().numpy()
+    pts = oracle.voxel_centres(s.geo, vox)
+    ref = np.empty((n, 2))
+    for j in np.unique(view):
+        m = view == j
+        ref[m] = oracle.project_points(s.Phat[j], pts[m])[:, :2]
+    fl = np.floor(ref)
+    band = np.any(np.minimum(ref - fl, fl + 1 - ref) < 1e-3, axis=1)
+    same = np.all(cell == fl.astype(np.int64), axis=1)
+    _report("index parity", pairs=n, excluded=int(band.sum()), mismatched=int((~same & ~band).sum()))
+    assert band.sum() < 0.01 * n
+    assert np.all(same[~band])
+
+
+@pytest.mark.parametrize("which", ["sumsq", "entropy_tv"])
+def test_losses_match_oracle(tiny, which):
+    from oracle import losses
+
+    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj)
+    vol_d = s.bp.forward(s.proj_d, s.theta_d)
+    vol = vol_d.cpu().numpy().astype(np.float64)
+    grad = torch.empty_like(vol_d)
+    if which == "sumsq":
+        loss = torch.empty(1, dtype=torch.float64, device=DEV)
+        gmc.gmc_loss_sumsq_grad(s.bp.plan, vol_d, grad, loss, s.bp.workspace)
+        L, d = losses.sumsq_grad(vol)
+        Lg = loss.cpu().numpy()[0]
+    else:
+        loss = torch.empty(5, dtype=torch.float64, device=DEV)
+        lam = 0.3
+        gmc.gmc_loss_entropy_tv(s.bp.plan, vol_d, lam, -0.01, 0.06, 1e-5, grad, loss, s.bp.workspace)
+        L, d, H, T = losses.entropy_tv(vol, lam, 64, -0.01, 0.06, 1e-5)
+        lv = loss.cpu().numpy()
+        Lg = lv[0]
+        assert lv[1] == pytest.approx(H, rel=1e-5)
+        assert lv[2] == pytest.approx(T, rel=1e-5)
+    _report("loss " + which, L=Lg, ref=L, grad_err=vol_err(grad.cpu().numpy(), d))
+    assert Lg == pytest.approx(L, rel=1e-5)
+    assert vol_err(grad.cpu().numpy(), d) <= VOL_TOL
+
+
+def test_bspline_and_adam_match_oracle():
+    from oracle import motion
+
+    rng = np.random.default_rng(3)
+    n_views, n_nodes = 496, 20
+    c = rng.standard_normal((6, n_nodes))
+    th = torch.empty((n_views, 6), dtype=torch.float64, device=DEV)
+    gmc.gmc_bspline_theta(n_views, n_nodes, _t(c, torch.float64), th)
+    assert np.allclose(th.cpu().numpy(), motion.theta_from_coeffs(c, n_views), rtol=1e-13, atol=1e-13)
+    g = rng.standard_normal((n_views, 6))
+    gc = torch.empty((6, n_nodes), dtype=torch.float64, device=DEV)
+    gmc.gmc_bspline_grad(n_views, n_nodes, _t(g, torch.float64), gc)
+    assert np.allclose(gc.cpu().numpy(), motion.coeff_grad(g, n_nodes), rtol=1e-12, atol=1e-12)
+    x, gg = rng.standard_normal(120), rng.standard_normal(120)
+    xd, md, vd = _t(x, torch.float64), torch.zeros(120, dtype=torch.float64, device=DEV), torch.zeros(
+        120, dtype=torch.float64, device=DEV)
+    xr, mr, vr = x.copy(), np.zeros(120), np.zeros(120)
+    for t in range(1, 4):
+        gmc.gmc_adam_step(xd, _t(gg * t, torch.float64), md, vd, t, 0.05)
+        xr, mr, vr = motion.adam_step(xr, gg * t, mr, vr, t, 0.05)
+    assert np.allclose(xd.cpu().numpy(), xr, rtol=1e-13, atol=1e-13)
+
+
+def test_autograd_function_matches_vjp(tiny):
+    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj)
+    theta = s.theta_d.clone().requires_grad_(True)
+    vol = backproject(theta, s.proj_d, s.bp)
+    w = torch.randn(vol.shape, device=DEV, dtype=torch.float32, generator=torch.Generator(DEV).manual_seed(1))
+    (vol * w).sum().backward()
+    g = s.bp.vjp(s.proj_d, s.theta_d, w.contiguous())
+    assert torch.equal(theta.grad, g)
+
+
+def test_invalid_geometry_raises_flag(tiny):
+    """A translation that puts voxels behind the source is reported by gmc_check."""
+    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj)
+    th = s.theta_d.clone()
+    th[0, 0] = 900.0   # moves the volume beyond the source of view 0
+    s.bp.forward(s.proj_d, th)
+    with pytest.raises(gmc.GmcError) as e:
+        s.bp.check()
+    assert e.value.status == -4
+    s.bp.forward(s.proj_d, s.theta_d)
+    s.bp.check()

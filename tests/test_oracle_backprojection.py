@@ -170,3 +170,21 @@ def test_short_scan_without_parker_weights_is_wrong():
     P = projection_matrices(scan)
     assert np.max(np.abs(oracle.backproject_points(geo, good, P, pts) - 0.02)) < 0.03 * 0.02
     assert np.max(np.abs(oracle.backproject_points(geo, bad, P, pts) - 0.02)) > 0.05 * 0.02
+
+
+def test_c_and_numpy_line_integrals_agree_under_motion():
+    """The input generator's two implementations (C with OpenMP, NumPy) on a moving head."""
+    import dataclasses
+
+    from synth import CONFIGS
+    from synth.configs import make_phantom
+    from synth.motion import random_motion
+    from synth.project import line_integrals_numpy
+
+    cfg = CONFIGS["head256"]
+    scan = dataclasses.replace(cfg, n_views=6, det_w=124, det_h=96, pitch_mm=3.08).scan
+    ph = make_phantom(cfg)
+    th, _ = random_motion(11, 6, 5, 3.0, 2.0)
+    a = line_integrals(scan, ph, th)
+    b = line_integrals_numpy(scan, ph, th, cull=False)
+    assert np.max(np.abs(a - b)) <= 1e-9 * np.max(np.abs(b))
