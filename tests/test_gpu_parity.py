@@ -78,13 +78,25 @@ def test_forward_tiny(tiny, weighting, flags):
     s.bp.check()
 
 
+def smooth_images(scan, seed):
+    """Smooth detector images: the exact-mode gradient (derivative of the bilinear interpolant)
+    jumps at pixel boundaries by the local second difference, so FP32 and FP64 positions that
+    fall on opposite sides of a boundary differ by that jump; on smooth data it is small."""
+    rng = np.random.default_rng(seed)
+    c = np.arange(scan.det_w)[None, None, :]
+    r = np.arange(scan.det_h)[None, :, None]
+    ph = rng.uniform(0, 6.28, (scan.n_views, 1, 1))
+    return (np.sin(0.05 * c + ph) * np.cos(0.04 * r + 0.5 * ph)).astype(np.float32)
+
+
 @pytest.mark.parametrize("weighting", ["fdk", "paper"])
 @pytest.mark.parametrize("grad_mode", ["paper", "exact"])
 def test_vjp_tiny_random_seed(tiny, weighting, grad_mode):
-    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj, weighting, grad_mode)
+    proj = tiny.proj if grad_mode == "paper" else smooth_images(tiny.scan, 4)
+    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, proj, weighting, grad_mode)
     delta = np.random.default_rng(99).standard_normal(tiny.grid.shape).astype(np.float32)
     g, gP = s.vjp(delta)
-    G = oracle.vjp(s.geo, tiny.proj, s.Phat, delta)
+    G = oracle.vjp(s.geo, proj, s.Phat, delta)
     ref = oracle.chain(G, s.dPhat)
     e = grad_err(g, ref)
     _report("vjp tiny", weighting=weighting, grad=grad_mode, err=np.array2string(e, precision=2), errP=mat_err(gP, G))
