@@ -60,7 +60,10 @@ enum { GMC_WEIGHT_PAPER = 0, GMC_WEIGHT_FDK = 1 };
  * border, per pixel). EXACT: the derivative of the bilinear interpolant. */
 enum { GMC_GRAD_PAPER = 0, GMC_GRAD_EXACT = 1 };
 /* geometry.flags bits */
-enum { GMC_FLAG_FORCE_GLOBAL = 1 };   /* testing: sample every view from global memory */
+enum {
+    GMC_FLAG_FORCE_GLOBAL = 1,  /* testing: gather every tap from global memory              */
+    GMC_FLAG_FORCE_EDGE = 2     /* testing: use the detector-border tap weights on every tile */
+};
 
 typedef struct {
     int32_t n_views, det_w, det_h;   /* projection stack [n_views][det_h][det_w]            */

@@ -17,6 +17,7 @@ STATUS = {0: "GMC_OK", -1: "GMC_E_INVALID", -2: "GMC_E_WORKSPACE", -3: "GMC_E_HI
 WEIGHT = {"paper": 0, "fdk": 1}
 GRAD = {"paper": 0, "exact": 1}
 FLAG_FORCE_GLOBAL = 1
+FLAG_FORCE_EDGE = 2
 
 EXPORTS = ["gmc_plan_create", "gmc_plan_destroy", "gmc_workspace_bytes", "gmc_plan_info", "gmc_compose",
            "gmc_backproject", "gmc_backproject_vjp", "gmc_prepare", "gmc_bp_forward", "gmc_bp_vjp",

@@ -47,7 +47,7 @@ gmc_status validate_geometry(const gmc_geometry* g) {
         return fail(GMC_E_INVALID, "weighting must be GMC_WEIGHT_PAPER or GMC_WEIGHT_FDK");
     if (g->grad_mode != GMC_GRAD_PAPER && g->grad_mode != GMC_GRAD_EXACT)
         return fail(GMC_E_INVALID, "grad_mode must be GMC_GRAD_PAPER or GMC_GRAD_EXACT");
-    if (g->flags & ~GMC_FLAG_FORCE_GLOBAL) return fail(GMC_E_INVALID, "unknown flag bits 0x%x", g->flags);
+    if (g->flags & ~(GMC_FLAG_FORCE_GLOBAL | GMC_FLAG_FORCE_EDGE)) return fail(GMC_E_INVALID, "unknown flag bits 0x%x", g->flags);
     const long long nvox = (long long)g->nx * g->ny * g->nz;
     if (nvox > (1LL << 40) || (long long)g->det_w * g->det_h > (1LL << 31))
         return fail(GMC_E_UNSUPPORTED, "volume or detector too large");

@@ -76,13 +76,75 @@ __device__ __forceinline__ void fetch_global(const float* __restrict__ img, int 
 
 }  // namespace
 
-// WEIGHT: GMC_WEIGHT_*; GRAD: GMC_GRAD_*; VJP: false = Eq. 3, true = Eq. 4-5.
+// ---------------------------------------------------------------- per-sample arithmetic
+
+// Homogeneous position of sample k of the thread's column, in the tile frame: identical in
+// every path (and in k_debug_project) so that every path sees the same detector position.
+struct Pos {
+    float uh, vh, rw, au, av;
+    int ci, ri;   // floor(uh), floor(vh) relative to the tile origin
+};
+
+__device__ __forceinline__ Pos sample_pos(float ub, float vb, float wb, float du, float dv, float dw, int k) {
+    const float kf = (float)k;
+    const float u = fmaf(kf, du, ub), vv = fmaf(kf, dv, vb), w = fmaf(kf, dw, wb);
+    Pos p;
+    p.rw = __builtin_amdgcn_rcpf(w);
+    p.uh = u * p.rw;
+    p.vh = vv * p.rw;
+    const float fu = floorf(p.uh), fv = floorf(p.vh);
+    p.au = p.uh - fu;
+    p.av = p.vh - fv;
+    p.ci = (int)fu;
+    p.ri = (int)fv;
+    return p;
+}
+
+// Row coefficients of Eq. 4 for one sample, accumulated into the 6 running sums of the column:
+// A = (g_u, g_v, g_u uh + g_v vh [+ 2 val]) * seed / w (Eq. 3 weighting) or * seed / w^3 (FDK).
+// gu, gv are doubled central differences and the seed is halved (paper gradient), or exact
+// bilinear derivatives with an unscaled seed (exact gradient).
+template <int WEIGHT, int GRAD>
+__device__ __forceinline__ void accumulate(const Pos& p, float seed, float val, float gu, float gv, int k,
+                                           float& S0, float& S1, float& S2, float& T0, float& T1, float& T2) {
+    float e, tt;
+    if (WEIGHT == GMC_WEIGHT_FDK) {
+        e = seed * (p.rw * p.rw * p.rw);
+        tt = fmaf(gu, p.uh, fmaf(gv, p.vh, (GRAD == GMC_GRAD_PAPER ? 4.0f : 2.0f) * val));
+    } else {
+        e = seed * p.rw;
+        tt = fmaf(gu, p.uh, gv * p.vh);
+    }
+    const float ek = e * (float)k;
+    S0 = fmaf(e, gu, S0);
+    S1 = fmaf(e, gv, S1);
+    S2 = fmaf(e, tt, S2);
+    T0 = fmaf(ek, gu, T0);
+    T1 = fmaf(ek, gv, T1);
+    T2 = fmaf(ek, tt, T2);
+}
+
+__device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+// ---------------------------------------------------------------- the kernel
+//
+// Per view v the workgroup (1) waits for its tile of view v (issued one view earlier into the
+// other LDS buffer) and synchronises, (2) issues the asynchronous global->LDS loads of view
+// v+1's tile, and the border tables of view v+1 if that tile crosses the detector border,
+// (3) samples view v from LDS while those loads are in flight. Tiles are filled with clamped
+// detector coordinates (the border pixel repeats outside the detector); the interior path
+// never touches the repeats, the border path masks them with the tables:
+//   column table (z, s): z = 1 inside the detector, 0 outside (bilinear taps of d, g_v);
+//                        s = 2 on the first and last column, 1 elsewhere (g_u, one-sided)
+//   row table likewise for rows (taps of d, g_u; s for g_v).
+// With repeated border pixels the central difference is 0 outside the detector by itself.
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
-__global__ void __launch_bounds__(THREADS) k_bp(BpArgs a) {
-    constexpr bool PLANES = VJP && GRAD == GMC_GRAD_PAPER;   // stage the gradient images
+__global__ void __launch_bounds__(THREADS, 3) k_bp(BpArgs a) {
     constexpr int PLANE = TP * TH;
-    __shared__ float sD[PLANE];
-    __shared__ float sG[PLANES ? 2 * PLANE : 1];
+    constexpr int NSEG = (TP + 63) / 64;
+    __shared__ float sT[2 * PLANE];
+    __shared__ float2 sCol[2 * TP];
+    __shared__ float2 sRow[2 * TH];
     __shared__ float sRed[VJP ? 2 * 4 * 12 : 1];
 
     const int blk = blockIdx.x;
@@ -103,7 +165,6 @@ __global__ void __launch_bounds__(THREADS) k_bp(BpArgs a) {
     float acc[BZ];
     float seed[VJP ? BZ : 1];
     if (VJP) {
-        // the paper gradient planes hold 2 g; fold the 1/2 into the seed
         const float sc = (GRAD == GMC_GRAD_PAPER) ? 0.5f : 1.0f;
 #pragma unroll
         for (int k = 0; k < BZ; ++k) seed[k] = (col_in && k0 + k < a.nz) ? sc * a.gvol[col_off + k] : 0.0f;
@@ -112,15 +173,49 @@ __global__ void __launch_bounds__(THREADS) k_bp(BpArgs a) {
         for (int k = 0; k < BZ; ++k) acc[k] = 0.0f;
     }
 
+    const BrickDesc* __restrict__ descs = a.desc + brick;
+    const long long dstride = a.n_bricks;
+
+    // issue view vv's tile loads into buffer buf (asynchronous, no registers)
+    auto stage = [&](const BrickDesc& D, int vv, int buf) {
+        if (D.mode != TILE_INTERIOR && D.mode != TILE_EDGE) return;
+        const float* __restrict__ img = a.proj + (long long)vv * a.plane;
+        float* tile = sT + buf * PLANE;
+        const int tw = D.tw, th = D.th;
+        for (int r = wave; r < th; r += 4) {
+            const int gr = min(max(D.ov + r, 0), a.H - 1);
+            const float* row = img + (long long)gr * a.W;
+#pragma unroll
+            for (int q = 0; q < NSEG; ++q) {
+                const int c = q * 64 + lane;
+                if (c < tw) {
+                    const int gc = min(max(D.ou + c, 0), a.W - 1);
+                    __builtin_amdgcn_global_load_lds(row + gc, tile + r * TP + q * 64, 4, 0, 0);
+                }
+            }
+        }
+        if (D.mode == TILE_EDGE) {
+            if (t < TP) {
+                const int gc = D.ou + t;
+                const float z = ((unsigned)gc < (unsigned)a.W) ? 1.0f : 0.0f;
+                const float sg = (gc == 0 || gc == a.W - 1) ? 2.0f : 1.0f;
+                sCol[buf * TP + t] = make_float2(z, sg);
+            } else if (t >= 128 && t < 128 + TH) {
+                const int gr = D.ov + (t - 128);
+                const float z = ((unsigned)gr < (unsigned)a.H) ? 1.0f : 0.0f;
+                const float sg = (gr == 0 || gr == a.H - 1) ? 2.0f : 1.0f;
+                sRow[buf * TH + (t - 128)] = make_float2(z, sg);
+            }
+        }
+    };
+
+    BrickDesc cur = descs[0];
+    stage(cur, 0, 0);
     int prev_ou = 0, prev_ov = 0;
     for (int v = 0; v < a.n_views; ++v) {
-        const BrickDesc* D = a.desc + (long long)v * a.n_bricks + brick;
-        float m[12];
-#pragma unroll
-        for (int e = 0; e < 12; ++e) m[e] = __builtin_nontemporal_load(&D->m[e]);
-        const int ou = D->ou, ov = D->ov, tw = D->tw, th = D->th;
-
-        __syncthreads();   // previous view's LDS reads are done
+        const int buf = v & 1;
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's tile loads of view v have landed in LDS
+        __syncthreads();                 // ... and everybody's; buffer buf^1 is free again
         if (VJP && v > 0 && t < 14) {
             float s;
             if (t < 12) {
@@ -131,106 +226,112 @@ __global__ void __launch_bounds__(THREADS) k_bp(BpArgs a) {
             }
             a.part[((long long)(v - 1) * a.n_bricks + brick) * PART_STRIDE + t] = s;
         }
-        prev_ou = ou;
-        prev_ov = ov;
+        BrickDesc nxt;
+        if (v + 1 < a.n_views) {
+            nxt = descs[(long long)(v + 1) * dstride];
+            stage(nxt, v + 1, buf ^ 1);
+        }
+        prev_ou = cur.ou;
+        prev_ov = cur.ov;
 
         float S0 = 0.f, S1 = 0.f, S2 = 0.f, T0 = 0.f, T1 = 0.f, T2 = 0.f;
-        if (tw != 0) {
-            const float* img = a.proj + (long long)v * a.plane;
-            const bool lds = tw > 0;
-            if (lds) {
-                for (int r = wave; r < th; r += 4) {
-                    const int gr = ov + r;
-                    const bool rin = (unsigned)gr < (unsigned)a.H;
-                    for (int c = lane; c < tw; c += 64) {
-                        const int gc = ou + c;
-                        float val = 0.0f;
-                        if (rin && (unsigned)gc < (unsigned)a.W) val = img[(long long)gr * a.W + gc];
-                        sD[r * TP + c] = val;
-                    }
-                }
-                __syncthreads();
-                if (PLANES) {
-                    for (int r = 1 + wave; r < th - 1; r += 4) {
-                        const int gr = ov + r;
-                        const bool rin = (unsigned)gr < (unsigned)a.H;
-                        for (int c = 1 + lane; c < tw - 1; c += 64) {
-                            const int gc = ou + c;
-                            float gu = 0.0f, gv = 0.0f;
-                            if (rin && (unsigned)gc < (unsigned)a.W) {
-                                const float ce = sD[r * TP + c];
-                                gu = grad_u2(sD[r * TP + c - 1], ce, sD[r * TP + c + 1], gc, a.W);
-                                gv = grad_u2(sD[(r - 1) * TP + c], ce, sD[(r + 1) * TP + c], gr, a.H);
-                            }
-                            sG[r * TP + c] = gu;
-                            sG[PLANE + r * TP + c] = gv;
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            const int twa = lds ? tw : -tw;
-            const float ub = fmaf(m[0], qx, fmaf(m[1], qy, m[3]));
-            const float vb = fmaf(m[4], qx, fmaf(m[5], qy, m[7]));
-            const float wb = fmaf(m[8], qx, fmaf(m[9], qy, m[11]));
-            const float du = m[2] * dz, dv = m[6] * dz, dw = m[10] * dz;
+        const float* m = cur.m;
+        const float ub = fmaf(m[0], qx, fmaf(m[1], qy, m[3]));
+        const float vb = fmaf(m[4], qx, fmaf(m[5], qy, m[7]));
+        const float wb = fmaf(m[8], qx, fmaf(m[9], qy, m[11]));
+        const float du = m[2] * dz, dv = m[6] * dz, dw = m[10] * dz;
+        const float* tile = sT + buf * PLANE;
+        const int cmax = cur.tw - 3, rmax = cur.th - 3;
+
+        if (cur.mode == TILE_INTERIOR) {
 #pragma unroll
             for (int k = 0; k < BZ; ++k) {
-                const float kf = (float)k;
-                const float u = fmaf(kf, du, ub), vv = fmaf(kf, dv, vb), w = fmaf(kf, dw, wb);
-                const float rw = __builtin_amdgcn_rcpf(w);
-                const float uh = u * rw, vh = vv * rw;
-                const float fu = floorf(uh), fv = floorf(vh);
-                const float au = uh - fu, av = vh - fv;
-                Taps tp;
-                if (lds) {
-                    const int ci = min(max((int)fu, 1), twa - 3);
-                    const int ri = min(max((int)fv, 1), th - 3);
-                    const int idx = ri * TP + ci;
-                    tp.d00 = sD[idx]; tp.d01 = sD[idx + 1]; tp.d10 = sD[idx + TP]; tp.d11 = sD[idx + TP + 1];
-                    if (PLANES) {
-                        tp.u00 = sG[idx]; tp.u01 = sG[idx + 1]; tp.u10 = sG[idx + TP]; tp.u11 = sG[idx + TP + 1];
-                        tp.v00 = sG[PLANE + idx]; tp.v01 = sG[PLANE + idx + 1];
-                        tp.v10 = sG[PLANE + idx + TP]; tp.v11 = sG[PLANE + idx + TP + 1];
-                    }
-                } else {
-                    fetch_global<PLANES>(img, a.W, a.H, (int)fv + ov, (int)fu + ou, tp);
-                }
-                const float e0 = tp.d01 - tp.d00, e1 = tp.d11 - tp.d10;
-                const float top = fmaf(au, e0, tp.d00), bot = fmaf(au, e1, tp.d10);
+                const Pos p = sample_pos(ub, vb, wb, du, dv, dw, k);
+                const int ci = min(max(p.ci, 1), cmax), ri = min(max(p.ri, 1), rmax);
+                const float* b = tile + ri * TP + ci;
+                const float d00 = b[0], d01 = b[1], d10 = b[TP], d11 = b[TP + 1];
+                const float e0 = d01 - d00, e1 = d11 - d10;
+                const float top = fmaf(p.au, e0, d00), bot = fmaf(p.au, e1, d10);
                 const float dtb = bot - top;
-                const float val = fmaf(av, dtb, top);
+                const float val = fmaf(p.av, dtb, top);
                 if (!VJP) {
-                    acc[k] += (WEIGHT == GMC_WEIGHT_FDK) ? val * (rw * rw) : val;
+                    acc[k] += (WEIGHT == GMC_WEIGHT_FDK) ? val * (p.rw * p.rw) : val;
                 } else {
                     float gu, gv;
-                    if (PLANES) {
-                        const float ut = fmaf(au, tp.u01 - tp.u00, tp.u00), ubm = fmaf(au, tp.u11 - tp.u10, tp.u10);
-                        gu = fmaf(av, ubm - ut, ut);
-                        const float vt = fmaf(au, tp.v01 - tp.v00, tp.v00), vbm = fmaf(au, tp.v11 - tp.v10, tp.v10);
-                        gv = fmaf(av, vbm - vt, vt);
+                    if (GRAD == GMC_GRAD_PAPER) {
+                        const float bm = b[-1], b2 = b[2], cm = b[TP - 1], c2 = b[TP + 2];
+                        const float a0 = b[-TP], a1 = b[-TP + 1], f0 = b[2 * TP], f1 = b[2 * TP + 1];
+                        // doubled central differences at the four taps, then bilinear
+                        gu = lerp(lerp(d01 - bm, b2 - d00, p.au), lerp(d11 - cm, c2 - d10, p.au), p.av);
+                        gv = lerp(lerp(d10 - a0, d11 - a1, p.au), lerp(f0 - d00, f1 - d01, p.au), p.av);
                     } else {
-                        // derivative of the bilinear interpolant
-                        gu = fmaf(av, e1 - e0, e0);
+                        gu = fmaf(p.av, e1 - e0, e0);
                         gv = dtb;
                     }
-                    // A = (g_u, g_v, -(g_u uh + g_v vh [+ 2 val])) scaled by seed / w (paper) or seed / w^3 (FDK);
-                    // with the paper planes g is doubled and the seed halved, so the value term is 4 val
-                    float e, tt;
-                    if (WEIGHT == GMC_WEIGHT_FDK) {
-                        e = seed[k] * (rw * rw * rw);
-                        tt = fmaf(gu, uh, fmaf(gv, vh, (GRAD == GMC_GRAD_PAPER ? 4.0f : 2.0f) * val));
+                    accumulate<WEIGHT, GRAD>(p, seed[k], val, gu, gv, k, S0, S1, S2, T0, T1, T2);
+                }
+            }
+        } else if (cur.mode == TILE_EDGE) {
+            const float2* ct = sCol + buf * TP;
+            const float2* rt = sRow + buf * TH;
+#pragma unroll
+            for (int k = 0; k < BZ; ++k) {
+                const Pos p = sample_pos(ub, vb, wb, du, dv, dw, k);
+                const int ci = min(max(p.ci, 1), cmax), ri = min(max(p.ri, 1), rmax);
+                const float* b = tile + ri * TP + ci;
+                const float2 c0 = ct[ci], c1 = ct[ci + 1], r0 = rt[ri], r1 = rt[ri + 1];
+                const float d00 = b[0], d01 = b[1], d10 = b[TP], d11 = b[TP + 1];
+                const float u0 = 1.0f - p.au, v0 = 1.0f - p.av;
+                // bilinear weights with the outside taps masked (z)
+                const float wc0 = u0 * c0.x, wc1 = p.au * c1.x, wr0 = v0 * r0.x, wr1 = p.av * r1.x;
+                const float val = fmaf(wr0, fmaf(wc0, d00, wc1 * d01), wr1 * fmaf(wc0, d10, wc1 * d11));
+                if (!VJP) {
+                    acc[k] += (WEIGHT == GMC_WEIGHT_FDK) ? val * (p.rw * p.rw) : val;
+                } else {
+                    float gu, gv;
+                    if (GRAD == GMC_GRAD_PAPER) {
+                        const float bm = b[-1], b2 = b[2], cm = b[TP - 1], c2 = b[TP + 2];
+                        const float a0 = b[-TP], a1 = b[-TP + 1], f0 = b[2 * TP], f1 = b[2 * TP + 1];
+                        // g_u: one-sided factor s per column, rows masked; g_v: s per row, columns masked
+                        const float sc0 = u0 * c0.y, sc1 = p.au * c1.y, sr0 = v0 * r0.y, sr1 = p.av * r1.y;
+                        gu = fmaf(wr0, fmaf(sc0, d01 - bm, sc1 * (b2 - d00)), wr1 * fmaf(sc0, d11 - cm, sc1 * (c2 - d10)));
+                        gv = fmaf(sr0, fmaf(wc0, d10 - a0, wc1 * (d11 - a1)), sr1 * fmaf(wc0, f0 - d00, wc1 * (f1 - d01)));
                     } else {
-                        e = seed[k] * rw;
-                        tt = fmaf(gu, uh, gv * vh);
+                        // derivative of the (masked) bilinear interpolant
+                        gu = fmaf(wr0, c1.x * d01 - c0.x * d00, wr1 * (c1.x * d11 - c0.x * d10));
+                        gv = fmaf(wc0, r1.x * d10 - r0.x * d00, wc1 * (r1.x * d11 - r0.x * d01));
                     }
-                    const float ek = e * kf;
-                    S0 = fmaf(e, gu, S0);
-                    S1 = fmaf(e, gv, S1);
-                    S2 = fmaf(e, tt, S2);
-                    T0 = fmaf(ek, gu, T0);
-                    T1 = fmaf(ek, gv, T1);
-                    T2 = fmaf(ek, tt, T2);
+                    accumulate<WEIGHT, GRAD>(p, seed[k], val, gu, gv, k, S0, S1, S2, T0, T1, T2);
+                }
+            }
+        } else if (cur.mode == TILE_GLOBAL) {
+            const float* __restrict__ img = a.proj + (long long)v * a.plane;
+#pragma unroll 1
+            for (int k = 0; k < BZ; ++k) {
+                const Pos p = sample_pos(ub, vb, wb, du, dv, dw, k);
+                Taps tp;
+                fetch_global<VJP && GRAD == GMC_GRAD_PAPER>(img, a.W, a.H, p.ri + cur.ov, p.ci + cur.ou, tp);
+                const float e0 = tp.d01 - tp.d00, e1 = tp.d11 - tp.d10;
+                const float top = fmaf(p.au, e0, tp.d00), bot = fmaf(p.au, e1, tp.d10);
+                const float dtb = bot - top;
+                const float val = fmaf(p.av, dtb, top);
+                // acc / seed are indexed dynamically here (this path is rare): select by k
+#pragma unroll
+                for (int kk = 0; kk < BZ; ++kk) {
+                    if (kk != k) continue;
+                    if (!VJP) {
+                        acc[kk] += (WEIGHT == GMC_WEIGHT_FDK) ? val * (p.rw * p.rw) : val;
+                    } else {
+                        float gu, gv;
+                        if (GRAD == GMC_GRAD_PAPER) {
+                            gu = lerp(lerp(tp.u00, tp.u01, p.au), lerp(tp.u10, tp.u11, p.au), p.av);
+                            gv = lerp(lerp(tp.v00, tp.v01, p.au), lerp(tp.v10, tp.v11, p.au), p.av);
+                        } else {
+                            gu = fmaf(p.av, e1 - e0, e0);
+                            gv = dtb;
+                        }
+                        accumulate<WEIGHT, GRAD>(p, seed[kk], val, gu, gv, kk, S0, S1, S2, T0, T1, T2);
+                    }
                 }
             }
         }
@@ -246,6 +347,7 @@ __global__ void __launch_bounds__(THREADS) k_bp(BpArgs a) {
                 for (int e = 0; e < 12; ++e) rb[e] = g[e];
             }
         }
+        if (v + 1 < a.n_views) cur = nxt;
     }
 
     if (VJP) {

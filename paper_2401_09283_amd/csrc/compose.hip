@@ -64,7 +64,7 @@ struct SetupArgs {
     const double* Phat;
     BrickDesc* desc;
     int* status;
-    int n_views, n_bricks, nbx, nby, bz, W, H, tp, th_max, force_global;
+    int n_views, n_bricks, nbx, nby, bz, W, H, tp, th_max, flags;
     double ox, oy, oz, dx, dy, dz;
 };
 
@@ -99,8 +99,8 @@ __global__ void k_setup(SetupArgs a) {
     if (bad || !(umax - umin < 1e6) || !(vmax - vmin < 1e6)) {
         for (int e = 0; e < 12; ++e) d.m[e] = 0.0f;
         d.ou = d.ov = 0;
-        d.tw = 0;
-        d.th = 0;
+        d.tw = d.th = 0;
+        d.mode = TILE_SKIP;
         atomicOr(a.status, 1);
         a.desc[idx] = d;
         return;
@@ -111,8 +111,6 @@ __global__ void k_setup(SetupArgs a) {
     const double rlo = floor(vmin), rhi = floor(vmax) + 1.0;
     const int ou = (int)clo - 2, ov = (int)rlo - 2;
     const int tw = (int)(chi - clo) + 5, th = (int)(rhi - rlo) + 5;
-    // detector position of this tile relative to the detector
-    const bool outside = (ou + tw <= 0) || (ou >= a.W) || (ov + th <= 0) || (ov >= a.H);
     // M = S * Phat * T_brick
     double rows[3][4];
     for (int c = 0; c < 4; ++c) {
@@ -128,13 +126,19 @@ __global__ void k_setup(SetupArgs a) {
     }
     d.ou = ou;
     d.ov = ov;
-    d.th = th;
-    if (outside)
-        d.tw = 0;
-    else if (a.force_global || tw > a.tp || th > a.th_max)
-        d.tw = -tw;
-    else
-        d.tw = tw;
+    const bool outside = (ou + tw <= 0) || (ou >= a.W) || (ov + th <= 0) || (ov >= a.H);
+    const bool inside = ou >= 0 && ov >= 0 && ou + tw <= a.W && ov + th <= a.H;
+    if (outside) {
+        d.mode = TILE_SKIP;
+    } else if ((a.flags & GMC_FLAG_FORCE_GLOBAL) || tw > a.tp || th > a.th_max) {
+        d.mode = TILE_GLOBAL;
+    } else if (inside && !(a.flags & GMC_FLAG_FORCE_EDGE)) {
+        d.mode = TILE_INTERIOR;
+    } else {
+        d.mode = TILE_EDGE;
+    }
+    d.tw = (int16_t)(tw < 32767 ? tw : 32767);
+    d.th = (int16_t)(th < 32767 ? th : 32767);
     a.desc[idx] = d;
 }
 
@@ -152,7 +156,7 @@ hipError_t launch_setup(const gmc_plan* p, const double* Phat, BrickDesc* desc, 
     a.H = p->g.det_h;
     a.tp = TILE_CFGS[p->tile_cfg].tp;
     a.th_max = TILE_CFGS[p->tile_cfg].th;
-    a.force_global = (p->g.flags & GMC_FLAG_FORCE_GLOBAL) ? 1 : 0;
+    a.flags = p->g.flags;
     a.ox = p->g.origin_mm[0];
     a.oy = p->g.origin_mm[1];
     a.oz = p->g.origin_mm[2];

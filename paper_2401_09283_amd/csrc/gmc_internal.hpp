@@ -18,10 +18,17 @@ constexpr int THREADS = BXY * BXY;
 // The local matrix m maps brick-local coordinates q (mm, relative to the centre of the
 // brick's first voxel) to (u'', v'', w) with u'' = u - ou*w and v'' = v - ov*w, so
 // u''/w is the detector column relative to the tile origin ou.
+enum TileMode : int32_t {
+    TILE_SKIP = 0,      // nothing to sample: the tile misses the detector, or w <= 0 (flagged)
+    TILE_INTERIOR = 1,  // tile inside the detector: plain bilinear taps from LDS
+    TILE_EDGE = 2,      // tile crosses the detector border: taps weighted by border tables
+    TILE_GLOBAL = 3     // tile larger than the LDS tile: taps gathered from global memory
+};
 struct BrickDesc {
     float m[12];
     int32_t ou, ov;   // detector column / row of tile index 0
-    int32_t tw, th;   // tile extent; tw == 0: nothing to sample (skip); tw < 0: sample from global memory
+    int16_t tw, th;   // tile extent (columns, rows)
+    int32_t mode;     // TileMode
 };
 static_assert(sizeof(BrickDesc) == 64, "descriptor must be 64 bytes");
 
@@ -34,6 +41,7 @@ struct TileCfg {
     int tp, th;
 };
 constexpr TileCfg TILE_CFGS[] = {{40, 40}, {80, 72}, {128, 96}};
+constexpr int TILE_CFG_MAX_TP = 128;
 constexpr int N_TILE_CFGS = 3;
 
 constexpr int LOSS_BLOCKS = 1024;   // blocks of the reduction kernels of the losses

@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FLAG_FORCE_GLOBAL, GRAD, WEIGHT, Geometry, GmcError, Work, check, lib  # noqa: F401
+from ._lib import FLAG_FORCE_EDGE, FLAG_FORCE_GLOBAL, GRAD, WEIGHT, Geometry, GmcError, Work, check, lib  # noqa: F401
 
 
 def _stream(stream=None):

@@ -67,7 +67,7 @@ def test_compose_matches_oracle(tiny):
 
 
 @pytest.mark.parametrize("weighting", ["fdk", "paper"])
-@pytest.mark.parametrize("flags", [0, gmc.FLAG_FORCE_GLOBAL])
+@pytest.mark.parametrize("flags", [0, gmc.FLAG_FORCE_GLOBAL, gmc.FLAG_FORCE_EDGE])
 def test_forward_tiny(tiny, weighting, flags):
     s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj, weighting, flags=flags)
     got = s.fwd()
@@ -91,15 +91,16 @@ def smooth_images(scan, seed):
 
 @pytest.mark.parametrize("weighting", ["fdk", "paper"])
 @pytest.mark.parametrize("grad_mode", ["paper", "exact"])
-def test_vjp_tiny_random_seed(tiny, weighting, grad_mode):
+@pytest.mark.parametrize("flags", [0, gmc.FLAG_FORCE_EDGE])
+def test_vjp_tiny_random_seed(tiny, weighting, grad_mode, flags):
     proj = tiny.proj if grad_mode == "paper" else smooth_images(tiny.scan, 4)
-    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, proj, weighting, grad_mode)
+    s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, proj, weighting, grad_mode, flags)
     delta = np.random.default_rng(99).standard_normal(tiny.grid.shape).astype(np.float32)
     g, gP = s.vjp(delta)
     G = oracle.vjp(s.geo, proj, s.Phat, delta)
     ref = oracle.chain(G, s.dPhat)
     e = grad_err(g, ref)
-    _report("vjp tiny", weighting=weighting, grad=grad_mode, err=np.array2string(e, precision=2), errP=mat_err(gP, G))
+    _report("vjp tiny", weighting=weighting, grad=grad_mode, flags=flags, err=np.array2string(e, precision=2), errP=mat_err(gP, G))
     assert np.all(e <= GRAD_TOL)
     assert mat_err(gP, G) <= GRAD_TOL
 
@@ -143,7 +144,7 @@ def test_ragged_grid_and_detector_edges():
     proj = rng.standard_normal((scan.n_views, scan.det_h, scan.det_w)).astype(np.float32)
     delta = rng.standard_normal(grid.shape).astype(np.float32)
     for weighting in ("fdk", "paper"):
-        for flags in (0, gmc.FLAG_FORCE_GLOBAL):
+        for flags in (0, gmc.FLAG_FORCE_GLOBAL, gmc.FLAG_FORCE_EDGE):
             s = Setup(scan, grid, P, th, proj, weighting, flags=flags)
             ev = vol_err(s.fwd(), oracle.backproject(s.geo, proj, s.Phat))
             g, _ = s.vjp(delta)
