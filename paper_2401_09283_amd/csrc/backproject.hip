@@ -82,7 +82,7 @@ __device__ __forceinline__ void fetch_global(const float* __restrict__ img, int 
 // every path (and in k_debug_project) so that every path sees the same detector position.
 struct Pos {
     float uh, vh, rw, au, av;
-    int ci, ri;   // floor(uh), floor(vh) relative to the tile origin
+    float fu, fv;   // floor(uh), floor(vh): cell relative to the tile origin
 };
 
 __device__ __forceinline__ Pos sample_pos(float ub, float vb, float wb, float du, float dv, float dw, int k) {
@@ -92,12 +92,20 @@ __device__ __forceinline__ Pos sample_pos(float ub, float vb, float wb, float du
     p.rw = __builtin_amdgcn_rcpf(w);
     p.uh = u * p.rw;
     p.vh = vv * p.rw;
-    const float fu = floorf(p.uh), fv = floorf(p.vh);
-    p.au = p.uh - fu;
-    p.av = p.vh - fv;
-    p.ci = (int)fu;
-    p.ri = (int)fv;
+    p.fu = floorf(p.uh);
+    p.fv = floorf(p.vh);
+    p.au = p.uh - p.fu;
+    p.av = p.vh - p.fv;
     return p;
+}
+
+// Linear LDS index of the sample's cell, clamped into the tile (a guard: the tile bounds
+// already contain every sample). Integer-valued floats keep it to med3 + one FMA + one cvt.
+template <int TP>
+__device__ __forceinline__ int tile_index(const Pos& p, float cmax, float rmax) {
+    const float cu = __builtin_amdgcn_fmed3f(p.fu, 1.0f, cmax);
+    const float cv = __builtin_amdgcn_fmed3f(p.fv, 1.0f, rmax);
+    return (int)fmaf(cv, (float)TP, cu);
 }
 
 // Row coefficients of Eq. 4 for one sample, accumulated into the 6 running sums of the column:
@@ -139,7 +147,9 @@ __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t
 //   row table likewise for rows (taps of d, g_u; s for g_v).
 // With repeated border pixels the central difference is 0 outside the detector by itself.
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
-__global__ void __launch_bounds__(THREADS, 3) k_bp(BpArgs a) {
+__global__ void __launch_bounds__(THREADS, 3)
+    k_bp(BpArgs a, const BrickDesc* __restrict__ desc, const float* __restrict__ proj, float* __restrict__ vol,
+         const float* __restrict__ gvol, float* __restrict__ part) {
     constexpr int PLANE = TP * TH;
     constexpr int NSEG = (TP + 63) / 64;
     __shared__ float sT[2 * PLANE];
@@ -156,7 +166,9 @@ __global__ void __launch_bounds__(THREADS, 3) k_bp(BpArgs a) {
 
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
-    const int li = t >> 4, lj = t & 15;
+    // each wave covers an 8 x 8 patch of columns, so its samples spread over fewer than 32
+    // detector columns of a tile row (fewer LDS bank conflicts)
+    const int li = 8 * (wave & 1) + (lane >> 3), lj = 8 * (wave >> 1) + (lane & 7);
     const int i = bi * BXY + li, j = bj * BXY + lj, k0 = bk * BZ;
     const bool col_in = (i < a.nx) && (j < a.ny);
     const float qx = (float)li * a.dx, qy = (float)lj * a.dy, dz = a.dz;
@@ -167,32 +179,38 @@ __global__ void __launch_bounds__(THREADS, 3) k_bp(BpArgs a) {
     if (VJP) {
         const float sc = (GRAD == GMC_GRAD_PAPER) ? 0.5f : 1.0f;
 #pragma unroll
-        for (int k = 0; k < BZ; ++k) seed[k] = (col_in && k0 + k < a.nz) ? sc * a.gvol[col_off + k] : 0.0f;
+        for (int k = 0; k < BZ; ++k) seed[k] = (col_in && k0 + k < a.nz) ? sc * gvol[col_off + k] : 0.0f;
     } else {
 #pragma unroll
         for (int k = 0; k < BZ; ++k) acc[k] = 0.0f;
     }
 
-    const BrickDesc* __restrict__ descs = a.desc + brick;
+    const BrickDesc* __restrict__ descs = desc + brick;
     const long long dstride = a.n_bricks;
 
-    // issue view vv's tile loads into buffer buf (asynchronous, no registers)
+    // issue view vv's tile loads into buffer buf (asynchronous, no registers). Rows are
+    // distributed over the four waves; the row loop runs on scalar registers, each lane
+    // carries one (clamped) detector column per 64-column segment.
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
     auto stage = [&](const BrickDesc& D, int vv, int buf) {
         if (D.mode != TILE_INTERIOR && D.mode != TILE_EDGE) return;
-        const float* __restrict__ img = a.proj + (long long)vv * a.plane;
+        const float* __restrict__ img = proj + (long long)vv * a.plane;
         float* tile = sT + buf * PLANE;
         const int tw = D.tw, th = D.th;
-        for (int r = wave; r < th; r += 4) {
+        int coff[NSEG];
+        bool cok[NSEG];
+#pragma unroll
+        for (int q = 0; q < NSEG; ++q) {
+            const int c = q * 64 + lane;
+            coff[q] = min(max(D.ou + c, 0), a.W - 1);
+            cok[q] = c < tw;
+        }
+        for (int r = wv; r < th; r += 4) {
             const int gr = min(max(D.ov + r, 0), a.H - 1);
             const float* row = img + (long long)gr * a.W;
 #pragma unroll
-            for (int q = 0; q < NSEG; ++q) {
-                const int c = q * 64 + lane;
-                if (c < tw) {
-                    const int gc = min(max(D.ou + c, 0), a.W - 1);
-                    __builtin_amdgcn_global_load_lds(row + gc, tile + r * TP + q * 64, 4, 0, 0);
-                }
-            }
+            for (int q = 0; q < NSEG; ++q)
+                if (cok[q]) __builtin_amdgcn_global_load_lds(row + coff[q], tile + r * TP + q * 64, 4, 0, 0);
         }
         if (D.mode == TILE_EDGE) {
             if (t < TP) {
@@ -224,7 +242,7 @@ __global__ void __launch_bounds__(THREADS, 3) k_bp(BpArgs a) {
             } else {
                 s = __int_as_float(t == 12 ? prev_ou : prev_ov);
             }
-            a.part[((long long)(v - 1) * a.n_bricks + brick) * PART_STRIDE + t] = s;
+            part[((long long)(v - 1) * a.n_bricks + brick) * PART_STRIDE + t] = s;
         }
         BrickDesc nxt;
         if (v + 1 < a.n_views) {
@@ -241,14 +259,16 @@ __global__ void __launch_bounds__(THREADS, 3) k_bp(BpArgs a) {
         const float wb = fmaf(m[8], qx, fmaf(m[9], qy, m[11]));
         const float du = m[2] * dz, dv = m[6] * dz, dw = m[10] * dz;
         const float* tile = sT + buf * PLANE;
-        const int cmax = cur.tw - 3, rmax = cur.th - 3;
+        const float cmax = (float)(cur.tw - 3), rmax = (float)(cur.th - 3);
 
         if (cur.mode == TILE_INTERIOR) {
+            // taps addressed from (row - 1, column - 1), so that every LDS offset is positive
+            const float* tile_m = tile - (TP + 1);
 #pragma unroll
             for (int k = 0; k < BZ; ++k) {
                 const Pos p = sample_pos(ub, vb, wb, du, dv, dw, k);
-                const int ci = min(max(p.ci, 1), cmax), ri = min(max(p.ri, 1), rmax);
-                const float* b = tile + ri * TP + ci;
+                const float* q = tile_m + tile_index<TP>(p, cmax, rmax);
+                const float* b = q + TP + 1;
                 const float d00 = b[0], d01 = b[1], d10 = b[TP], d11 = b[TP + 1];
                 const float e0 = d01 - d00, e1 = d11 - d10;
                 const float top = fmaf(p.au, e0, d00), bot = fmaf(p.au, e1, d10);
@@ -259,11 +279,13 @@ __global__ void __launch_bounds__(THREADS, 3) k_bp(BpArgs a) {
                 } else {
                     float gu, gv;
                     if (GRAD == GMC_GRAD_PAPER) {
-                        const float bm = b[-1], b2 = b[2], cm = b[TP - 1], c2 = b[TP + 2];
-                        const float a0 = b[-TP], a1 = b[-TP + 1], f0 = b[2 * TP], f1 = b[2 * TP + 1];
-                        // doubled central differences at the four taps, then bilinear
+                        const float bm = q[TP], b2 = q[TP + 3], cm = q[2 * TP], c2 = q[2 * TP + 3];
+                        const float a0 = q[1], a1 = q[2], f0 = q[3 * TP + 1], f1 = q[3 * TP + 2];
+                        // doubled central differences at the four taps, interpolated bilinearly;
+                        // along v the rows are interpolated first: rows r0-1 and r0+2 give
+                        // (1-b)(row(r0+1) - row(r0-1)) + b (row(r0+2) - row(r0))
                         gu = lerp(lerp(d01 - bm, b2 - d00, p.au), lerp(d11 - cm, c2 - d10, p.au), p.av);
-                        gv = lerp(lerp(d10 - a0, d11 - a1, p.au), lerp(f0 - d00, f1 - d01, p.au), p.av);
+                        gv = lerp(bot - lerp(a0, a1, p.au), lerp(f0, f1, p.au) - top, p.av);
                     } else {
                         gu = fmaf(p.av, e1 - e0, e0);
                         gv = dtb;
@@ -277,7 +299,8 @@ __global__ void __launch_bounds__(THREADS, 3) k_bp(BpArgs a) {
 #pragma unroll
             for (int k = 0; k < BZ; ++k) {
                 const Pos p = sample_pos(ub, vb, wb, du, dv, dw, k);
-                const int ci = min(max(p.ci, 1), cmax), ri = min(max(p.ri, 1), rmax);
+                const int ci = (int)__builtin_amdgcn_fmed3f(p.fu, 1.0f, cmax);
+                const int ri = (int)__builtin_amdgcn_fmed3f(p.fv, 1.0f, rmax);
                 const float* b = tile + ri * TP + ci;
                 const float2 c0 = ct[ci], c1 = ct[ci + 1], r0 = rt[ri], r1 = rt[ri + 1];
                 const float d00 = b[0], d01 = b[1], d10 = b[TP], d11 = b[TP + 1];
@@ -305,12 +328,12 @@ __global__ void __launch_bounds__(THREADS, 3) k_bp(BpArgs a) {
                 }
             }
         } else if (cur.mode == TILE_GLOBAL) {
-            const float* __restrict__ img = a.proj + (long long)v * a.plane;
+            const float* __restrict__ img = proj + (long long)v * a.plane;
 #pragma unroll 1
             for (int k = 0; k < BZ; ++k) {
                 const Pos p = sample_pos(ub, vb, wb, du, dv, dw, k);
                 Taps tp;
-                fetch_global<VJP && GRAD == GMC_GRAD_PAPER>(img, a.W, a.H, p.ri + cur.ov, p.ci + cur.ou, tp);
+                fetch_global<VJP && GRAD == GMC_GRAD_PAPER>(img, a.W, a.H, (int)p.fv + cur.ov, (int)p.fu + cur.ou, tp);
                 const float e0 = tp.d01 - tp.d00, e1 = tp.d11 - tp.d10;
                 const float top = fmaf(p.au, e0, tp.d00), bot = fmaf(p.au, e1, tp.d10);
                 const float dtb = bot - top;
@@ -361,10 +384,10 @@ __global__ void __launch_bounds__(THREADS, 3) k_bp(BpArgs a) {
             } else {
                 s = __int_as_float(t == 12 ? prev_ou : prev_ov);
             }
-            a.part[((long long)(v - 1) * a.n_bricks + brick) * PART_STRIDE + t] = s;
+            part[((long long)(v - 1) * a.n_bricks + brick) * PART_STRIDE + t] = s;
         }
     } else if (col_in) {
-        float* out = a.vol + col_off;
+        float* out = vol + col_off;
 #pragma unroll
         for (int k = 0; k < BZ; ++k)
             if (k0 + k < a.nz) out[k] = acc[k];
@@ -379,18 +402,18 @@ hipError_t launch_cfg(const gmc_plan* p, const BpArgs& a, bool vjp, hipStream_t 
     const int W = p->g.weighting, G = p->g.grad_mode;
     if (!vjp) {
         if (W == GMC_WEIGHT_FDK)
-            k_bp<TP, TH, BZ, GMC_WEIGHT_FDK, GMC_GRAD_PAPER, false><<<grid, THREADS, 0, s>>>(a);
+            k_bp<TP, TH, BZ, GMC_WEIGHT_FDK, GMC_GRAD_PAPER, false><<<grid, THREADS, 0, s>>>(a, a.desc, a.proj, a.vol, a.gvol, a.part);
         else
-            k_bp<TP, TH, BZ, GMC_WEIGHT_PAPER, GMC_GRAD_PAPER, false><<<grid, THREADS, 0, s>>>(a);
+            k_bp<TP, TH, BZ, GMC_WEIGHT_PAPER, GMC_GRAD_PAPER, false><<<grid, THREADS, 0, s>>>(a, a.desc, a.proj, a.vol, a.gvol, a.part);
     } else {
         if (W == GMC_WEIGHT_FDK && G == GMC_GRAD_PAPER)
-            k_bp<TP, TH, BZ, GMC_WEIGHT_FDK, GMC_GRAD_PAPER, true><<<grid, THREADS, 0, s>>>(a);
+            k_bp<TP, TH, BZ, GMC_WEIGHT_FDK, GMC_GRAD_PAPER, true><<<grid, THREADS, 0, s>>>(a, a.desc, a.proj, a.vol, a.gvol, a.part);
         else if (W == GMC_WEIGHT_FDK)
-            k_bp<TP, TH, BZ, GMC_WEIGHT_FDK, GMC_GRAD_EXACT, true><<<grid, THREADS, 0, s>>>(a);
+            k_bp<TP, TH, BZ, GMC_WEIGHT_FDK, GMC_GRAD_EXACT, true><<<grid, THREADS, 0, s>>>(a, a.desc, a.proj, a.vol, a.gvol, a.part);
         else if (G == GMC_GRAD_PAPER)
-            k_bp<TP, TH, BZ, GMC_WEIGHT_PAPER, GMC_GRAD_PAPER, true><<<grid, THREADS, 0, s>>>(a);
+            k_bp<TP, TH, BZ, GMC_WEIGHT_PAPER, GMC_GRAD_PAPER, true><<<grid, THREADS, 0, s>>>(a, a.desc, a.proj, a.vol, a.gvol, a.part);
         else
-            k_bp<TP, TH, BZ, GMC_WEIGHT_PAPER, GMC_GRAD_EXACT, true><<<grid, THREADS, 0, s>>>(a);
+            k_bp<TP, TH, BZ, GMC_WEIGHT_PAPER, GMC_GRAD_EXACT, true><<<grid, THREADS, 0, s>>>(a, a.desc, a.proj, a.vol, a.gvol, a.part);
     }
     return hipGetLastError();
 }
@@ -432,15 +455,11 @@ __global__ void k_debug_project(const BrickDesc* __restrict__ desc, int n_bricks
     const float vb = fmaf(D.m[4], qx, fmaf(D.m[5], qy, D.m[7]));
     const float wb = fmaf(D.m[8], qx, fmaf(D.m[9], qy, D.m[11]));
     const float du = D.m[2] * dz, dv = D.m[6] * dz, dw = D.m[10] * dz;
-    const float kf = (float)kk;
-    const float u = fmaf(kf, du, ub), vv = fmaf(kf, dv, vb), w = fmaf(kf, dw, wb);
-    const float rw = __builtin_amdgcn_rcpf(w);
-    const float uh = u * rw, vh = vv * rw;
-    const float fu = floorf(uh), fv = floorf(vh);
-    cell[2 * q] = (int)fu + D.ou;
-    cell[2 * q + 1] = (int)fv + D.ov;
-    frac[2 * q] = uh - fu;
-    frac[2 * q + 1] = vh - fv;
+    const Pos p = sample_pos(ub, vb, wb, du, dv, dw, kk);
+    cell[2 * q] = (int)p.fu + D.ou;
+    cell[2 * q + 1] = (int)p.fv + D.ov;
+    frac[2 * q] = p.au;
+    frac[2 * q + 1] = p.av;
 }
 
 hipError_t launch_debug_project(const gmc_plan* p, const BrickDesc* desc, long long n, const int64_t* voxel,
