@@ -24,15 +24,27 @@ __device__ __forceinline__ float dpp_add(float v) {
     return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
 }
 
-// Sum over the 64 lanes of a wavefront; the total ends in lane 63.
-__device__ __forceinline__ float wave_sum_to_last(float v) {
-    v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-    v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-    v = dpp_add<0x124, 0xF>(v);  // row_ror:4
-    v = dpp_add<0x128, 0xF>(v);  // row_ror:8
-    v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
-    v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
-    return v;
+// Reduce-scatter of 12 per-lane values over the 64 lanes of a wavefront. Swapping 32-lane
+// halves (v_permlane32_swap) pairs value i with i+6, swapping 16-lane rows (v_permlane16_swap)
+// pairs i with i+3, and four DPP steps finish each 16-lane row. On return, every lane of row q
+// (lanes 16q..16q+15) holds the wave totals of values 3q, 3q+1, 3q+2 in out[0..2].
+__device__ __forceinline__ void wave_reduce12(const float g[12], float out[3]) {
+    float h[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(g[i]), __float_as_uint(g[i + 6]), false, false);
+        h[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(h[i]), __float_as_uint(h[i + 3]), false, false);
+        float k = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+        k = dpp_add<0xB1, 0xF>(k);   // quad_perm [1,0,3,2]
+        k = dpp_add<0x4E, 0xF>(k);   // quad_perm [2,3,0,1]
+        k = dpp_add<0x124, 0xF>(k);  // row_ror:4
+        k = dpp_add<0x128, 0xF>(k);  // row_ror:8
+        out[i] = k;
+    }
 }
 
 __device__ __forceinline__ float pix(const float* __restrict__ img, int W, int H, int r, int c) {
@@ -264,6 +276,36 @@ __global__ void __launch_bounds__(THREADS, 3)
         if (cur.mode == TILE_INTERIOR) {
             // taps addressed from (row - 1, column - 1), so that every LDS offset is positive
             const float* tile_m = tile - (TP + 1);
+            if (!VJP) {
+                // positions of all samples first, then all LDS reads, then the arithmetic:
+                // the reads of one column are in flight together
+                int idx[BZ];
+                float au[BZ], av[BZ], ww[BZ];
+#pragma unroll
+                for (int k = 0; k < BZ; ++k) {
+                    const Pos p = sample_pos(ub, vb, wb, du, dv, dw, k);
+                    idx[k] = tile_index<TP>(p, cmax, rmax);
+                    au[k] = p.au;
+                    av[k] = p.av;
+                    ww[k] = (WEIGHT == GMC_WEIGHT_FDK) ? p.rw * p.rw : 1.0f;
+                }
+                float d00[BZ], d01[BZ], d10[BZ], d11[BZ];
+#pragma unroll
+                for (int k = 0; k < BZ; ++k) {
+                    const float* b = tile_m + idx[k] + TP + 1;
+                    d00[k] = b[0];
+                    d01[k] = b[1];
+                    d10[k] = b[TP];
+                    d11[k] = b[TP + 1];
+                }
+#pragma unroll
+                for (int k = 0; k < BZ; ++k) {
+                    const float top = fmaf(au[k], d01[k] - d00[k], d00[k]);
+                    const float bot = fmaf(au[k], d11[k] - d10[k], d10[k]);
+                    const float val = fmaf(av[k], bot - top, top);
+                    acc[k] = (WEIGHT == GMC_WEIGHT_FDK) ? fmaf(val, ww[k], acc[k]) : acc[k] + val;
+                }
+            } else {
 #pragma unroll
             for (int k = 0; k < BZ; ++k) {
                 const Pos p = sample_pos(ub, vb, wb, du, dv, dw, k);
@@ -274,24 +316,21 @@ __global__ void __launch_bounds__(THREADS, 3)
                 const float top = fmaf(p.au, e0, d00), bot = fmaf(p.au, e1, d10);
                 const float dtb = bot - top;
                 const float val = fmaf(p.av, dtb, top);
-                if (!VJP) {
-                    acc[k] += (WEIGHT == GMC_WEIGHT_FDK) ? val * (p.rw * p.rw) : val;
+                float gu, gv;
+                if (GRAD == GMC_GRAD_PAPER) {
+                    const float bm = q[TP], b2 = q[TP + 3], cm = q[2 * TP], c2 = q[2 * TP + 3];
+                    const float a0 = q[1], a1 = q[2], f0 = q[3 * TP + 1], f1 = q[3 * TP + 2];
+                    // doubled central differences at the four taps, interpolated bilinearly;
+                    // along v the rows are interpolated first: rows r0-1 and r0+2 give
+                    // (1-b)(row(r0+1) - row(r0-1)) + b (row(r0+2) - row(r0))
+                    gu = lerp(lerp(d01 - bm, b2 - d00, p.au), lerp(d11 - cm, c2 - d10, p.au), p.av);
+                    gv = lerp(bot - lerp(a0, a1, p.au), lerp(f0, f1, p.au) - top, p.av);
                 } else {
-                    float gu, gv;
-                    if (GRAD == GMC_GRAD_PAPER) {
-                        const float bm = q[TP], b2 = q[TP + 3], cm = q[2 * TP], c2 = q[2 * TP + 3];
-                        const float a0 = q[1], a1 = q[2], f0 = q[3 * TP + 1], f1 = q[3 * TP + 2];
-                        // doubled central differences at the four taps, interpolated bilinearly;
-                        // along v the rows are interpolated first: rows r0-1 and r0+2 give
-                        // (1-b)(row(r0+1) - row(r0-1)) + b (row(r0+2) - row(r0))
-                        gu = lerp(lerp(d01 - bm, b2 - d00, p.au), lerp(d11 - cm, c2 - d10, p.au), p.av);
-                        gv = lerp(bot - lerp(a0, a1, p.au), lerp(f0, f1, p.au) - top, p.av);
-                    } else {
-                        gu = fmaf(p.av, e1 - e0, e0);
-                        gv = dtb;
-                    }
-                    accumulate<WEIGHT, GRAD>(p, seed[k], val, gu, gv, k, S0, S1, S2, T0, T1, T2);
+                    gu = fmaf(p.av, e1 - e0, e0);
+                    gv = dtb;
                 }
+                accumulate<WEIGHT, GRAD>(p, seed[k], val, gu, gv, k, S0, S1, S2, T0, T1, T2);
+            }
             }
         } else if (cur.mode == TILE_EDGE) {
             const float2* ct = sCol + buf * TP;
@@ -362,12 +401,13 @@ __global__ void __launch_bounds__(THREADS, 3)
             // G'' rows r: (qx S_r, qy S_r, dz T_r, S_r); row 2 carries the minus sign of Eq. 4
             float g[12] = {qx * S0, qy * S0, dz * T0, S0, qx * S1, qy * S1, dz * T1, S1,
                            -qx * S2, -qy * S2, -dz * T2, -S2};
-#pragma unroll
-            for (int e = 0; e < 12; ++e) g[e] = wave_sum_to_last(g[e]);
-            if (lane == 63) {
-                float* rb = sRed + (v & 1) * 48 + wave * 12;
-#pragma unroll
-                for (int e = 0; e < 12; ++e) rb[e] = g[e];
+            float red[3] = {0.0f, 0.0f, 0.0f};
+            if (cur.mode != TILE_SKIP) wave_reduce12(g, red);
+            if ((lane & 15) == 0) {
+                float* rb = sRed + (v & 1) * 48 + wave * 12 + 3 * (lane >> 4);
+                rb[0] = red[0];
+                rb[1] = red[1];
+                rb[2] = red[2];
             }
         }
         if (v + 1 < a.n_views) cur = nxt;
