@@ -91,8 +91,8 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2401_09283_amd import gmc
     from paper_2401_09283_amd.autograd import Backprojector
+    from paper_2401_09283_amd.solver import MotionSolver, SolverConfig
     from synth import CONFIGS, make_case
 
     cfg = CONFIGS[args.config]
@@ -104,62 +104,28 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     bp = Backprojector.from_case(case, device=dev)
-    plan, ws = bp.plan, bp.workspace
-    n, nn = cfg.n_views, cfg.n_nodes
     proj = torch.from_numpy(case.proj).to(dev)
-    P = bp.P
-    coeffs = torch.zeros((6, nn), dtype=torch.float64, device=dev)
-    m_ = torch.zeros_like(coeffs)
-    v_ = torch.zeros_like(coeffs)
-    gc = torch.empty_like(coeffs)
-    theta = torch.empty((n, 6), dtype=torch.float64, device=dev)
-    gtheta = torch.empty((n, 6), dtype=torch.float64, device=dev)
-    vol = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
-    gvol = torch.empty_like(vol)
-    loss = torch.empty(5, dtype=torch.float64, device=dev)
-    lo, hi, eps = -0.01, 0.06, 1e-5
-
-    # lambda: equal gradient norms of the entropy and TV terms at theta = 0 (one sync, untimed)
-    gmc.gmc_bspline_theta(n, nn, coeffs, theta)
-    gmc.gmc_prepare(plan, P, theta, 1, ws)
-    gmc.gmc_bp_forward(plan, proj, vol, ws)
-    gmc.gmc_loss_entropy_tv(plan, vol, 0.0, lo, hi, eps, gvol, loss, ws)
-    l0 = loss.cpu().numpy()
-    lam = float(np.sqrt(l0[3] / max(l0[4], 1e-300)))
+    solver = MotionSolver(bp, proj, SolverConfig(n_nodes=cfg.n_nodes, lr=args.lr, loss="entropy_tv"))
+    solver.calibrate()   # TV weight from the seed norms at theta = 0 (one sync, untimed)
 
     ev = {k: [] for k in ("f0", "f1", "v0", "v1", "s0", "s1")}
 
-    def step(it, timed):
+    def step(timed):
         e = {k: torch.cuda.Event(enable_timing=True) for k in ev} if timed else None
         if timed:
             e["s0"].record()
-        gmc.gmc_bspline_theta(n, nn, coeffs, theta)
-        gmc.gmc_prepare(plan, P, theta, 1, ws)
-        if timed:
-            e["f0"].record()
-        gmc.gmc_bp_forward(plan, proj, vol, ws)
-        if timed:
-            e["f1"].record()
-        gmc.gmc_loss_entropy_tv(plan, vol, lam, lo, hi, eps, gvol, loss, ws)
-        if timed:
-            e["v0"].record()
-        gmc.gmc_bp_vjp(plan, proj, gvol, ws)
-        if timed:
-            e["v1"].record()
-        gmc.gmc_bp_vjp_finish(plan, gtheta, None, ws)
-        gmc.gmc_bspline_grad(n, nn, gtheta, gc)
-        gmc.gmc_adam_step(coeffs, gc, m_, v_, it + 1, args.lr)
+        solver.iteration(events=e)
         if timed:
             e["s1"].record()
             for k in ev:
                 ev[k].append(e[k])
 
-    for it in range(args.warmup):
-        step(it, False)
+    for _ in range(args.warmup):
+        step(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for it in range(args.warmup, args.warmup + args.steps):
-        step(it, True)
+    for _ in range(args.steps):
+        step(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     bp.check()
