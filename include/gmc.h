@@ -162,10 +162,16 @@ gmc_status gmc_gd_step(int64_t n, double* x, const double* g, int32_t n_iter, do
 gmc_status gmc_debug_project(const gmc_plan* plan, int64_t n, const int64_t* voxel, const int32_t* view,
                              int32_t* cell, float* frac, const void* workspace, void* hip_stream);
 
-/* Serving: one persistent launch over several (plan, phase) work items.
- * phase 0 = backprojection (writes vol), 1 = VJP (writes grad_theta, grad_P if set).
- * Every item needs its own workspace. Items may have different geometries; results
- * are identical to the corresponding single calls. */
+/* Serving: several (plan, phase) work items in one backprojection launch.
+ * phase 0 = backprojection (writes vol), 1 = VJP (writes grad_theta, and grad_P if set).
+ * For each item the call first runs gmc_prepare (skipped when flags has GMC_WORK_PREPARED:
+ * the caller already ran gmc_prepare on that workspace, with with_deriv = 1 for phase 1),
+ * then ONE kernel launch processes the voxel bricks of all items of a phase together
+ * (items are grouped by phase, weighting and gradient mode, at most 16 per launch), then
+ * the VJP items are reduced and chained. Every item needs its own workspace. Items may
+ * have different geometries; each result is bitwise identical to the corresponding single
+ * call. */
+enum { GMC_WORK_PREPARED = 1 };
 typedef struct {
     const gmc_plan* plan;
     const float* proj;
@@ -177,6 +183,7 @@ typedef struct {
     double* grad_P;          /* phase 1 optional output (or NULL)    */
     void* workspace;
     int32_t phase;
+    int32_t flags;           /* GMC_WORK_* bits                      */
 } gmc_work;
 gmc_status gmc_launch_batch(const gmc_work* items, int32_t n_items, void* hip_stream);
 

@@ -18,6 +18,7 @@ WEIGHT = {"paper": 0, "fdk": 1}
 GRAD = {"paper": 0, "exact": 1}
 FLAG_FORCE_GLOBAL = 1
 FLAG_FORCE_EDGE = 2
+WORK_PREPARED = 1
 
 EXPORTS = ["gmc_plan_create", "gmc_plan_destroy", "gmc_workspace_bytes", "gmc_plan_info", "gmc_compose",
            "gmc_backproject", "gmc_backproject_vjp", "gmc_prepare", "gmc_bp_forward", "gmc_bp_vjp",
@@ -43,7 +44,7 @@ class Work(ctypes.Structure):
     _fields_ = [("plan", ctypes.c_void_p), ("proj", ctypes.c_void_p), ("P", ctypes.c_void_p),
                 ("theta", ctypes.c_void_p), ("vol", ctypes.c_void_p), ("grad_vol", ctypes.c_void_p),
                 ("grad_theta", ctypes.c_void_p), ("grad_P", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
-                ("phase", ctypes.c_int32)]
+                ("phase", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 _lib = None

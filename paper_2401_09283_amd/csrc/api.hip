@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "gmc_internal.hpp"
 
@@ -59,7 +60,10 @@ void nominal_tile_extent(const gmc_plan* p, const double* P, int* tw_max, int* t
     const gmc_geometry& g = p->g;
     int twm = 0, thm = 0;
     const double ext[3] = {(BXY - 1) * g.voxel_mm[0], (BXY - 1) * g.voxel_mm[1], (p->bz - 1) * g.voxel_mm[2]};
-    for (int v = 0; v < g.n_views; ++v) {
+    // every view for short scans, a subsample of long ones (a sizing heuristic: a tile that
+    // exceeds the chosen LDS tile at run time is sampled from global memory instead)
+    const int vstride = std::max(1, g.n_views / 128);
+    for (int v = 0; v < g.n_views; v += vstride) {
         const double* Ph = P + 12 * v;
         for (int b = 0; b < p->n_bricks; ++b) {
             const int bj = b % p->nby, bi = (b / p->nby) % p->nbx, bk = b / (p->nby * p->nbx);
@@ -373,16 +377,60 @@ gmc_status gmc_debug_project(const gmc_plan* plan, int64_t n, const int64_t* vox
 
 gmc_status gmc_launch_batch(const gmc_work* items, int32_t n_items, void* hip_stream) {
     if (n_items < 0 || (n_items > 0 && !items)) return fail(GMC_E_INVALID, "bad item list");
+    hipStream_t s = (hipStream_t)hip_stream;
+    // validate everything before launching anything
     for (int32_t q = 0; q < n_items; ++q) {
         const gmc_work& it = items[q];
-        gmc_status st;
-        if (it.phase == 0)
-            st = gmc_backproject(it.plan, it.proj, it.P, it.theta, it.vol, it.workspace, hip_stream);
-        else if (it.phase == 1)
-            st = gmc_backproject_vjp(it.plan, it.proj, it.P, it.theta, it.grad_vol, it.grad_theta, it.grad_P,
-                                     it.workspace, hip_stream);
-        else
-            st = fail(GMC_E_INVALID, "item %d: phase must be 0 or 1", q);
+        gmc_status st = check_plan_ws(it.plan, it.workspace);
+        if (st != GMC_OK) return fail(st, "item %d: %s", q, g_last_error.c_str());
+        if (it.phase != 0 && it.phase != 1) return fail(GMC_E_INVALID, "item %d: phase must be 0 or 1", q);
+        if (it.flags & ~GMC_WORK_PREPARED) return fail(GMC_E_INVALID, "item %d: unknown flag bits", q);
+        if (!it.proj || !(it.flags & GMC_WORK_PREPARED ? true : (it.P && it.theta)))
+            return fail(GMC_E_INVALID, "item %d: NULL input", q);
+        if (it.phase == 0 && !it.vol) return fail(GMC_E_INVALID, "item %d: NULL vol", q);
+        if (it.phase == 1 && (!it.grad_vol || !it.grad_theta)) return fail(GMC_E_INVALID, "item %d: NULL gradient", q);
+        for (int32_t r = 0; r < q; ++r)
+            if (items[r].workspace == it.workspace)
+                return fail(GMC_E_WORKSPACE, "items %d and %d share a workspace", r, q);
+    }
+    for (int32_t q = 0; q < n_items; ++q) {
+        const gmc_work& it = items[q];
+        if (it.flags & GMC_WORK_PREPARED) continue;
+        gmc_status st = gmc_prepare(it.plan, it.P, it.theta, it.phase == 1 ? 1 : 0, it.workspace, hip_stream);
+        if (st != GMC_OK) return st;
+    }
+    // one launch per (phase, weighting, gradient mode) group and at most MAX_BATCH items
+    std::vector<bool> done(n_items, false);
+    for (int32_t q0 = 0; q0 < n_items; ++q0) {
+        if (done[q0]) continue;
+        const gmc_work& lead = items[q0];
+        BatchTable tab;
+        tab.n = 0;
+        tab.total = 0;
+        int cfg = 0;
+        for (int32_t q = q0; q < n_items && tab.n < MAX_BATCH; ++q) {
+            const gmc_work& it = items[q];
+            if (done[q] || it.phase != lead.phase || it.plan->g.weighting != lead.plan->g.weighting ||
+                it.plan->g.grad_mode != lead.plan->g.grad_mode)
+                continue;
+            BpArgs ba = bp_args(it.plan, it.proj, carve(it.plan, it.workspace));
+            ba.vol = it.vol;
+            ba.gvol = it.grad_vol;
+            tab.item[tab.n] = ba;
+            tab.begin[tab.n] = tab.total;
+            tab.total += it.plan->n_bricks;
+            tab.n++;
+            cfg = std::max(cfg, it.plan->tile_cfg);
+            done[q] = true;
+        }
+        tab.per_xcd = (tab.total + 7) / 8;
+        hipError_t e = launch_bp_batch(cfg, lead.plan->g.weighting, lead.plan->g.grad_mode, tab, lead.phase == 1, s);
+        if (e != hipSuccess) return hip_fail(e, "batched backprojection");
+    }
+    for (int32_t q = 0; q < n_items; ++q) {
+        const gmc_work& it = items[q];
+        if (it.phase != 1) continue;
+        gmc_status st = gmc_bp_vjp_finish(it.plan, it.grad_theta, it.grad_P, it.workspace, hip_stream);
         if (st != GMC_OK) return st;
     }
     return GMC_OK;

@@ -158,20 +158,27 @@ __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t
 //                        s = 2 on the first and last column, 1 elsewhere (g_u, one-sided)
 //   row table likewise for rows (taps of d, g_u; s for g_v).
 // With repeated border pixels the central difference is 0 outside the detector by itself.
+__device__ __forceinline__ BrickDesc load_desc(const __attribute__((address_space(4))) BrickDesc* p) {
+    BrickDesc d;
+#pragma unroll
+    for (int e = 0; e < 12; ++e) d.m[e] = p->m[e];
+    d.ou = p->ou;
+    d.ov = p->ov;
+    d.tw = p->tw;
+    d.th = p->th;
+    d.mode = p->mode;
+    return d;
+}
+
+// The work of one brick over all views; shared by the single-plan kernel and the batched one.
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
-__global__ void __launch_bounds__(THREADS, 3)
-    k_bp(BpArgs a, const BrickDesc* __restrict__ desc, const float* __restrict__ proj, float* __restrict__ vol,
-         const float* __restrict__ gvol, float* __restrict__ part) {
+__device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __restrict__ desc,
+                                         const float* __restrict__ proj, float* __restrict__ vol,
+                                         const float* __restrict__ gvol, float* __restrict__ part, const int brick,
+                                         float* __restrict__ sT, float2* __restrict__ sCol, float2* __restrict__ sRow,
+                                         float* __restrict__ sRed) {
     constexpr int PLANE = TP * TH;
     constexpr int NSEG = (TP + 63) / 64;
-    __shared__ float sT[2 * PLANE];
-    __shared__ float2 sCol[2 * TP];
-    __shared__ float2 sRow[2 * TH];
-    __shared__ float sRed[VJP ? 2 * 4 * 12 : 1];
-
-    const int blk = blockIdx.x;
-    const int brick = (blk & 7) * a.per_xcd + (blk >> 3);
-    if (brick >= a.n_bricks) return;
     const int bj = brick % a.nby;
     const int bi = (brick / a.nby) % a.nbx;
     const int bk = brick / (a.nby * a.nbx);
@@ -197,7 +204,10 @@ __global__ void __launch_bounds__(THREADS, 3)
         for (int k = 0; k < BZ; ++k) acc[k] = 0.0f;
     }
 
-    const BrickDesc* __restrict__ descs = desc + brick;
+    // the descriptors are read-only for the whole launch: read them through the constant
+    // address space so that they arrive with scalar loads whatever the caller's pointer provenance
+    typedef const __attribute__((address_space(4))) BrickDesc ConstDesc;
+    ConstDesc* descs = (ConstDesc*)(desc + brick);
     const long long dstride = a.n_bricks;
 
     // issue view vv's tile loads into buffer buf (asynchronous, no registers). Rows are
@@ -239,7 +249,7 @@ __global__ void __launch_bounds__(THREADS, 3)
         }
     };
 
-    BrickDesc cur = descs[0];
+    BrickDesc cur = load_desc(descs);
     stage(cur, 0, 0);
     int prev_ou = 0, prev_ov = 0;
     for (int v = 0; v < a.n_views; ++v) {
@@ -258,7 +268,7 @@ __global__ void __launch_bounds__(THREADS, 3)
         }
         BrickDesc nxt;
         if (v + 1 < a.n_views) {
-            nxt = descs[(long long)(v + 1) * dstride];
+            nxt = load_desc(descs + (long long)(v + 1) * dstride);
             stage(nxt, v + 1, buf ^ 1);
         }
         prev_ou = cur.ou;
@@ -434,6 +444,41 @@ __global__ void __launch_bounds__(THREADS, 3)
     }
 }
 
+template <int TP, int TH>
+struct BpShared {
+    float sT[2 * TP * TH];
+    float2 sCol[2 * TP];
+    float2 sRow[2 * TH];
+    float sRed[2 * 4 * 12];
+};
+
+template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
+__global__ void __launch_bounds__(THREADS, 3)
+    k_bp(BpArgs a, const BrickDesc* __restrict__ desc, const float* __restrict__ proj, float* __restrict__ vol,
+         const float* __restrict__ gvol, float* __restrict__ part) {
+    __shared__ BpShared<TP, TH> sh;
+    const int blk = blockIdx.x;
+    const int brick = (blk & 7) * a.per_xcd + (blk >> 3);
+    if (brick >= a.n_bricks) return;
+    bp_brick<TP, TH, BZ, WEIGHT, GRAD, VJP>(a, desc, proj, vol, gvol, part, brick, sh.sT, sh.sCol, sh.sRow, sh.sRed);
+}
+
+// Several plans in one launch: the bricks of all items form one index space (item q owns
+// [begin_q, begin_q + n_bricks_q)), mapped to XCDs like a single plan's bricks.
+template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
+__global__ void __launch_bounds__(THREADS, 3) k_bp_batch(BatchTable tab) {
+    __shared__ BpShared<TP, TH> sh;
+    const int blk = blockIdx.x;
+    const int g = (blk & 7) * tab.per_xcd + (blk >> 3);
+    if (g >= tab.total) return;
+    int q = 0;
+    for (int e = 1; e < tab.n; ++e)
+        if (g >= tab.begin[e]) q = e;
+    const BpArgs& a = tab.item[q];
+    bp_brick<TP, TH, BZ, WEIGHT, GRAD, VJP>(a, a.desc, a.proj, a.vol, a.gvol, a.part, g - tab.begin[q], sh.sT, sh.sCol,
+                                           sh.sRow, sh.sRed);
+}
+
 namespace {
 
 template <int TP, int TH, int BZ>
@@ -459,6 +504,37 @@ hipError_t launch_cfg(const gmc_plan* p, const BpArgs& a, bool vjp, hipStream_t 
 }
 
 }  // namespace
+
+template <int TP, int TH, int BZ>
+hipError_t launch_batch_cfg(int W, int G, const BatchTable& tab, bool vjp, hipStream_t s) {
+    const unsigned grid = 8u * (unsigned)tab.per_xcd;
+    if (!vjp) {
+        if (W == GMC_WEIGHT_FDK)
+            k_bp_batch<TP, TH, BZ, GMC_WEIGHT_FDK, GMC_GRAD_PAPER, false><<<grid, THREADS, 0, s>>>(tab);
+        else
+            k_bp_batch<TP, TH, BZ, GMC_WEIGHT_PAPER, GMC_GRAD_PAPER, false><<<grid, THREADS, 0, s>>>(tab);
+    } else {
+        if (W == GMC_WEIGHT_FDK && G == GMC_GRAD_PAPER)
+            k_bp_batch<TP, TH, BZ, GMC_WEIGHT_FDK, GMC_GRAD_PAPER, true><<<grid, THREADS, 0, s>>>(tab);
+        else if (W == GMC_WEIGHT_FDK)
+            k_bp_batch<TP, TH, BZ, GMC_WEIGHT_FDK, GMC_GRAD_EXACT, true><<<grid, THREADS, 0, s>>>(tab);
+        else if (G == GMC_GRAD_PAPER)
+            k_bp_batch<TP, TH, BZ, GMC_WEIGHT_PAPER, GMC_GRAD_PAPER, true><<<grid, THREADS, 0, s>>>(tab);
+        else
+            k_bp_batch<TP, TH, BZ, GMC_WEIGHT_PAPER, GMC_GRAD_EXACT, true><<<grid, THREADS, 0, s>>>(tab);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bp_batch(int tile_cfg, int weighting, int grad_mode, const BatchTable& tab, bool vjp, hipStream_t s) {
+    if (tab.n < 1 || tab.n > MAX_BATCH || tab.total < 1) return hipErrorInvalidValue;
+    switch (tile_cfg) {
+        case 0: return launch_batch_cfg<TILE_CFGS[0].tp, TILE_CFGS[0].th, 16>(weighting, grad_mode, tab, vjp, s);
+        case 1: return launch_batch_cfg<TILE_CFGS[1].tp, TILE_CFGS[1].th, 16>(weighting, grad_mode, tab, vjp, s);
+        case 2: return launch_batch_cfg<TILE_CFGS[2].tp, TILE_CFGS[2].th, 16>(weighting, grad_mode, tab, vjp, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_bp(const gmc_plan* p, const BpArgs& a, bool vjp, hipStream_t s) {
     if (p->bz != 16) return hipErrorInvalidValue;

@@ -71,11 +71,22 @@ struct BpArgs {
     long long plane;     // W*H
 };
 
+// Several plans in one launch (serving): bricks of item q are [begin[q], begin[q] + n_bricks).
+constexpr int MAX_BATCH = 16;
+struct BatchTable {
+    BpArgs item[MAX_BATCH];
+    int begin[MAX_BATCH];
+    int n, total, per_xcd;
+};
+
 // launchers (return hipError_t of the launch)
 hipError_t launch_compose(const double* theta, const double* P, double* Phat, double* dPhat, int n_views,
                           hipStream_t s);
 hipError_t launch_setup(const gmc_plan* p, const double* Phat, BrickDesc* desc, int* status, hipStream_t s);
 hipError_t launch_bp(const gmc_plan* p, const BpArgs& a, bool vjp, hipStream_t s);
+// one launch over all items of tab; every plan must share weighting and gradient mode, and
+// tile_cfg must be at least each plan's own tile configuration
+hipError_t launch_bp_batch(int tile_cfg, int weighting, int grad_mode, const BatchTable& tab, bool vjp, hipStream_t s);
 hipError_t launch_reduce_chain(const gmc_plan* p, const float* part, const double* dPhat, double* G,
                                double* grad_theta, double* grad_P, hipStream_t s);
 hipError_t launch_debug_project(const gmc_plan* p, const BrickDesc* desc, long long n, const int64_t* voxel,

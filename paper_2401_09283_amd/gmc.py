@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FLAG_FORCE_EDGE, FLAG_FORCE_GLOBAL, GRAD, WEIGHT, Geometry, GmcError, Work, check, lib  # noqa: F401
+from ._lib import FLAG_FORCE_EDGE, FLAG_FORCE_GLOBAL, GRAD, WORK_PREPARED, WEIGHT, Geometry, GmcError, Work, check, lib  # noqa: F401
 
 
 def _stream(stream=None):
@@ -215,14 +215,15 @@ def gmc_launch_batch(items, stream=None):
         w = arr[q]
         w.plan = plan.handle
         w.proj = _ptr(it["proj"], torch.float32, plan.proj_shape, "proj")
-        w.P = _ptr(it["P"], torch.float64, (n, 3, 4), "P")
-        w.theta = _ptr(it["theta"], torch.float64, (n, 6), "theta")
+        w.P = _ptr(it.get("P"), torch.float64, (n, 3, 4), "P", True)
+        w.theta = _ptr(it.get("theta"), torch.float64, (n, 6), "theta", True)
         w.vol = _ptr(it.get("vol"), torch.float32, plan.vol_shape, "vol", True)
         w.grad_vol = _ptr(it.get("grad_vol"), torch.float32, plan.vol_shape, "grad_vol", True)
         w.grad_theta = _ptr(it.get("grad_theta"), torch.float64, (n, 6), "grad_theta", True)
         w.grad_P = _ptr(it.get("grad_P"), torch.float64, (n, 3, 4), "grad_P", True)
         w.workspace = _ws(plan, it["workspace"])
         w.phase = int(it["phase"])
+        w.flags = int(it.get("flags", 0))
         keep.append(it)
     check(lib().gmc_launch_batch(arr, len(items), _stream(stream)), "gmc_launch_batch")
 

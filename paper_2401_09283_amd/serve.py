@@ -1,0 +1,352 @@
+"""Continuous-batching service for motion-estimation requests (one GPU).
+
+Requests arrive over time (e.g. a Poisson stream). The server admits a waiting request as
+soon as an active slot is free and its HBM footprint (projections, volumes, optimiser state,
+workspace) fits the budget, keeps everything of an admitted request resident on the device,
+and advances all active requests together: every scheduler tick is one solver iteration
+(spline -> compose -> backprojection -> loss -> VJP -> chain -> Adam) for every active
+request, with ONE backprojection launch and ONE VJP launch over the voxel bricks of all of
+them (gmc_launch_batch). Requests of different volume and view counts share the launches;
+each request's arithmetic is the same as when it runs alone, so its result is bitwise
+identical. A request that finishes its iterations retires and frees its memory; the next
+tick admits new arrivals.
+
+The scheduler is independent of the GPU: ``Server`` drives an executor with four calls
+(footprint, admit, step, release), so its admission and retirement logic is tested on the
+CPU with a fake executor and a fake clock.
+
+``python -m paper_2401_09283_amd.serve`` runs the synthetic serving workload (Poisson
+arrivals at 2 requests/s drawn from 128^3 x 248, 256^3 x 496 and 384^3 x 496 views, 30
+iterations each) batched and as sequential plain solves, and prints latency percentiles
+and throughput of both.
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import math
+import time
+from typing import Callable
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float                    # seconds after the start of the run
+    n_iter: int
+    inputs: Callable[[], dict] | dict  # dict(geometry=..., proj=np f32, P=np f64, n_nodes=...) or a factory
+    # filled by the server
+    t_admit: float | None = None
+    t_done: float | None = None
+    status: str = "waiting"           # waiting | active | done | failed
+    error: str | None = None
+    result: dict | None = None
+    iters_done: int = 0
+    state: object = None
+
+    @property
+    def latency(self):
+        return None if self.t_done is None else self.t_done - self.arrival
+
+
+class Server:
+    """Continuous batching over an executor (see module docstring)."""
+
+    def __init__(self, executor, hbm_budget_bytes: int, max_active: int = 16, clock=None, sleep=None):
+        self.ex = executor
+        self.budget = int(hbm_budget_bytes)
+        self.max_active = int(max_active)
+        self.clock = clock or time.perf_counter
+        self.sleep = sleep or time.sleep
+        self.used = 0
+        self.ticks = 0
+        self.batch_sizes = []
+
+    def run(self, requests):
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        pending = list(reqs)
+        waiting, active = [], []
+        t0 = self.clock()
+        now = lambda: self.clock() - t0  # noqa: E731
+        while pending or waiting or active:
+            t = now()
+            while pending and pending[0].arrival <= t:
+                waiting.append(pending.pop(0))
+            # FIFO admission by slots and HBM footprint
+            while waiting and len(active) < self.max_active:
+                r = waiting[0]
+                need = self.ex.footprint(r)
+                if need > self.budget:
+                    waiting.pop(0)
+                    r.status, r.error, r.t_done = "failed", "footprint %d exceeds the budget" % need, now()
+                    continue
+                if self.used + need > self.budget:
+                    break
+                waiting.pop(0)
+                try:
+                    self.ex.admit(r)
+                except Exception as e:  # a request that cannot be set up fails alone
+                    r.status, r.error, r.t_done = "failed", "admit: %s" % e, now()
+                    continue
+                self.used += need
+                r.t_admit = now()
+                r.status = "active"
+                active.append(r)
+            if not active:
+                if pending:
+                    self.sleep(max(0.0, pending[0].arrival - now()))
+                continue
+            try:
+                self.ex.step(active)
+            except Exception as e:
+                # a failed tick fails its requests and frees their slots; others go on
+                for r in active:
+                    r.status, r.error, r.t_done = "failed", "step: %s" % e, now()
+                    self._release(r)
+                active = []
+                continue
+            self.ticks += 1
+            self.batch_sizes.append(len(active))
+            t = now()
+            still = []
+            for r in active:
+                r.iters_done += 1
+                if r.iters_done >= r.n_iter:
+                    r.result = self.ex.result(r)
+                    r.status, r.t_done = "done", t
+                    self._release(r)
+                else:
+                    still.append(r)
+            active = still
+        return reqs
+
+    def _release(self, r):
+        try:
+            self.used -= self.ex.footprint(r)
+            self.ex.release(r)
+        except Exception:
+            pass
+
+
+def summarize(reqs, t_end=None):
+    done = [r for r in reqs if r.status == "done"]
+    lat = np.array([r.latency for r in done]) if done else np.zeros(0)
+    span = (max(r.t_done for r in done) - min(r.arrival for r in reqs)) if done else float("nan")
+    return dict(requests=len(reqs), done=len(done), failed=sum(r.status == "failed" for r in reqs),
+                p50_s=float(np.percentile(lat, 50)) if len(lat) else None,
+                p99_s=float(np.percentile(lat, 99)) if len(lat) else None,
+                mean_s=float(lat.mean()) if len(lat) else None,
+                throughput_req_per_s=len(done) / span if done else None, makespan_s=span)
+
+
+# ---------------------------------------------------------------------------------- GPU side
+
+class GpuExecutor:
+    """Device state of each admitted request and the batched iteration."""
+
+    def __init__(self, device="cuda", lr=0.05, loss="entropy_tv"):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.lr = lr
+        self.loss = loss
+
+    def _inputs(self, r):
+        if callable(r.inputs):
+            r.inputs = r.inputs()
+        return r.inputs
+
+    def footprint(self, r):
+        """Bytes of HBM an admitted request holds: projections, volume and seed, workspace,
+        and 1 MiB for parameters and optimiser state."""
+        inp = self._inputs(r)
+        if "footprint" not in inp:
+            from . import gmc
+
+            g = inp["geometry"]
+            plan = gmc.Plan(g)   # the workspace size does not depend on the matrices
+            nvox = g.nx * g.ny * g.nz
+            inp["footprint"] = int(inp["proj"].nbytes + 2 * 4 * nvox + plan.workspace_bytes + (1 << 20))
+            plan.close()
+        return inp["footprint"]
+
+    def admit(self, r):
+        from .autograd import Backprojector
+        from .solver import MotionSolver, SolverConfig
+
+        inp = self._inputs(r)
+        g = inp["geometry"]
+        torch = self.torch
+        bp = Backprojector(g.n_views, g.det_w, g.det_h, (g.nx, g.ny, g.nz), tuple(g.voxel_mm), tuple(g.origin_mm),
+                           inp["P"], weighting=g.weighting, grad_mode=g.grad_mode, device=self.device)
+        proj = torch.from_numpy(inp["proj"]).to(self.device)
+        s = MotionSolver(bp, proj, SolverConfig(n_iter=r.n_iter, n_nodes=inp["n_nodes"], lr=self.lr, loss=self.loss))
+        s.calibrate()
+        r.state = s
+
+    def step(self, reqs):
+        from . import gmc
+
+        fwd, vjp = [], []
+        for r in reqs:
+            s = r.state
+            gmc.gmc_bspline_theta(s.n_views, s.cfg.n_nodes, s.coeffs, s.theta)
+            gmc.gmc_prepare(s.bp.plan, s.bp.P, s.theta, 1, s.bp.workspace)
+            fwd.append(dict(plan=s.bp.plan, proj=s.proj, vol=s.vol, workspace=s.bp.workspace, phase=0,
+                            flags=gmc.WORK_PREPARED))
+        gmc.gmc_launch_batch(fwd)
+        for r in reqs:
+            r.state._loss(r.state.lam)
+        for r in reqs:
+            s = r.state
+            vjp.append(dict(plan=s.bp.plan, proj=s.proj, grad_vol=s.gvol, grad_theta=s.gtheta,
+                            workspace=s.bp.workspace, phase=1, flags=gmc.WORK_PREPARED))
+        gmc.gmc_launch_batch(vjp)
+        for r in reqs:
+            s = r.state
+            gmc.gmc_bspline_grad(s.n_views, s.cfg.n_nodes, s.gtheta, s.gc)
+            s.it += 1
+            gmc.gmc_adam_step(s.coeffs, s.gc, s.m, s.v, s.it, s.cfg.lr, s.cfg.beta1, s.cfg.beta2, s.cfg.adam_eps)
+        self.torch.cuda.synchronize()
+
+    def result(self, r):
+        from . import gmc
+
+        s = r.state
+        gmc.gmc_bspline_theta(s.n_views, s.cfg.n_nodes, s.coeffs, s.theta)
+        return dict(coeffs=s.coeffs.cpu().numpy(), theta=s.theta.cpu().numpy())
+
+    def release(self, r):
+        r.state = None
+
+
+def run_sequential(requests, device="cuda", lr=0.05, loss="entropy_tv", clock=None, sleep=None):
+    """Plain solves one after another in arrival order (single-request launches)."""
+    import torch
+
+    ex = GpuExecutor(device, lr, loss)
+    clock = clock or time.perf_counter
+    sleep = sleep or time.sleep
+    reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+    t0 = clock()
+    for r in reqs:
+        wait = r.arrival - (clock() - t0)
+        if wait > 0:
+            sleep(wait)
+        ex.admit(r)
+        r.t_admit = clock() - t0
+        s = r.state
+        for _ in range(r.n_iter):
+            s.iteration()
+        torch.cuda.synchronize()
+        r.result = ex.result(r)
+        r.t_done = clock() - t0
+        r.status = "done"
+        ex.release(r)
+    return reqs
+
+
+# ---------------------------------------------------------------------------------- workload
+
+SERVE_SIZES = ("serve128", "serve256", "serve384")
+
+
+def poisson_requests(n, lam, seed, n_iter, sizes=SERVE_SIZES, size_seed=None):
+    """Arrival times of a Poisson stream (rate lam per second) and uniformly drawn sizes."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / lam, n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    pick = rng.integers(0, len(sizes), n)
+    return [(int(i), float(arrivals[i]), sizes[int(pick[i])], n_iter) for i in range(n)]
+
+
+def make_request_inputs(size, i):
+    """Inputs of request i: its own phantom (seed 1000 + i) and motion (seed 2000 + i)."""
+    from synth import CONFIGS, make_case
+
+    from . import gmc
+
+    cfg = CONFIGS[size]
+    c = make_case(cfg, phantom_seed=1000 + i, motion_seed=2000 + i)
+    g = gmc.make_geometry(cfg.n_views, cfg.det_w, cfg.det_h, c.grid.shape, c.grid.voxel_mm, c.grid.origin_mm)
+    return dict(geometry=g, proj=c.proj, P=c.P, n_nodes=cfg.n_nodes, theta_true=c.theta_true, size=size)
+
+
+def main(argv=None):
+    import argparse
+    import concurrent.futures as cf
+
+    import torch
+
+    from .solver import reprojection_error
+
+    ap = argparse.ArgumentParser(description="continuous-batching motion-estimation service")
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--rate", type=float, default=2.0)
+    ap.add_argument("--iters", type=int, default=30)
+    ap.add_argument("--seed", type=int, default=40)
+    ap.add_argument("--max-active", type=int, default=16)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--skip-sequential", action="store_true")
+    args = ap.parse_args(argv)
+
+    spec = poisson_requests(args.requests, args.rate, args.seed, args.iters)
+    t = time.perf_counter()
+    inputs = [None] * len(spec)
+    with cf.ThreadPoolExecutor(4) as pool:
+        futs = {pool.submit(make_request_inputs, s[2], s[0]): s[0] for s in spec}
+        for n, f in enumerate(cf.as_completed(futs)):
+            inputs[futs[f]] = f.result()
+            if (n + 1) % 8 == 0:
+                print("serve: generated %d/%d requests (%.0f s)" % (n + 1, len(spec), time.perf_counter() - t),
+                      flush=True)
+
+    def fresh():
+        return [Request(rid, arr, it, dict(inputs[rid])) for rid, arr, size, it in spec]
+
+    # warm the kernels once
+    warm = GpuExecutor()
+    w = Request(-1, 0.0, 1, dict(inputs[0]))
+    warm.admit(w)
+    warm.step([w])
+    warm.release(w)
+    torch.cuda.synchronize()
+
+    out = dict(requests=args.requests, rate_per_s=args.rate, iters=args.iters, seed=args.seed,
+               sizes={s: sum(1 for x in spec if x[2] == s) for s in SERVE_SIZES})
+    srv = Server(GpuExecutor(), int(args.budget_gb * 1e9), args.max_active)
+    reqs = srv.run(fresh())
+    out["batched"] = summarize(reqs)
+    out["batched"]["mean_batch"] = float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0
+    out["batched"]["rpe_final_mm_mean"] = float(np.mean([
+        reprojection_error(inputs[r.rid]["P"], r.result["theta"], inputs[r.rid]["theta_true"],
+                           _pitch(inputs[r.rid]["size"])) for r in reqs if r.status == "done"]))
+    print("serve: batched %s" % json.dumps(out["batched"]), flush=True)
+    if not args.skip_sequential:
+        print("serve: sequential plain solves", flush=True)
+        seq = run_sequential(fresh())
+        out["sequential"] = summarize(seq)
+        out["sequential"]["rpe_final_mm_mean"] = float(np.mean([
+            reprojection_error(inputs[r.rid]["P"], r.result["theta"], inputs[r.rid]["theta_true"],
+                               _pitch(inputs[r.rid]["size"])) for r in seq]))
+        same = all(np.array_equal(a.result["coeffs"], b.result["coeffs"])
+                   for a, b in zip(sorted(reqs, key=lambda r: r.rid), sorted(seq, key=lambda r: r.rid))
+                   if a.status == "done")
+        out["identical_results"] = bool(same)
+    out["rpe_initial_mm_mean"] = float(np.mean([
+        reprojection_error(inputs[i]["P"], np.zeros_like(inputs[i]["theta_true"]), inputs[i]["theta_true"],
+                           _pitch(inputs[i]["size"])) for i in range(len(spec))]))
+    print(json.dumps(out), flush=True)
+
+
+def _pitch(size):
+    from synth import CONFIGS
+
+    return CONFIGS[size].pitch_mm
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,126 @@
+"""The serving scheduler on the CPU: a fake executor and a fake clock (no GPU)."""
+import pytest
+
+from paper_2401_09283_amd.serve import Request, Server, poisson_requests, summarize
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-9)
+
+
+class FakeExecutor:
+    """Each tick costs `tick` seconds; footprints are given per request; can be told to fail."""
+
+    def __init__(self, clock, tick=0.1, fail_admit=(), fail_step_at=None):
+        self.clock, self.tick = clock, tick
+        self.fail_admit = set(fail_admit)
+        self.fail_step_at = fail_step_at
+        self.steps = 0
+        self.log = []
+        self.resident = set()
+
+    def footprint(self, r):
+        return r.inputs["bytes"]
+
+    def admit(self, r):
+        if r.rid in self.fail_admit:
+            raise RuntimeError("bad geometry")
+        self.resident.add(r.rid)
+        self.log.append(("admit", r.rid, self.clock()))
+
+    def step(self, reqs):
+        self.steps += 1
+        if self.fail_step_at is not None and self.steps == self.fail_step_at:
+            raise RuntimeError("device error")
+        self.log.append(("step", tuple(r.rid for r in reqs), self.clock()))
+        self.clock.t += self.tick
+
+    def result(self, r):
+        return {"rid": r.rid}
+
+    def release(self, r):
+        self.resident.discard(r.rid)
+        self.log.append(("release", r.rid, self.clock()))
+
+
+def make(reqspec):
+    return [Request(rid, arr, it, {"bytes": b}) for rid, arr, it, b in reqspec]
+
+
+def test_fifo_admission_by_slots_and_memory_and_continuous_batching():
+    clk = FakeClock()
+    ex = FakeExecutor(clk, tick=0.1)
+    srv = Server(ex, hbm_budget_bytes=100, max_active=2, clock=clk, sleep=clk.sleep)
+    reqs = srv.run(make([(0, 0.0, 3, 60), (1, 0.05, 2, 30), (2, 0.06, 2, 50), (3, 1.0, 1, 10)]))
+    assert all(r.status == "done" for r in reqs)
+    steps = [e[1] for e in ex.log if e[0] == "step"]
+    # 0 alone; 1 joins at the next tick (arrived while 0 was on the GPU); 2 waits for memory
+    assert steps[0] == (0,)
+    assert steps[1] == (0, 1)
+    assert (2,) in steps or any(2 in s for s in steps)
+    first2 = next(i for i, s in enumerate(steps) if 2 in s)
+    # 2 (50 B) only fits after 0 (60 B) retired
+    release0 = next(i for i, e in enumerate(ex.log) if e[0] == "release" and e[1] == 0)
+    admit2 = next(i for i, e in enumerate(ex.log) if e[0] == "admit" and e[1] == 2)
+    assert admit2 > release0
+    assert srv.used == 0 and not ex.resident
+    assert first2 >= 2
+    s = summarize(reqs)
+    assert s["done"] == 4 and s["p50_s"] > 0
+
+
+def test_budget_never_exceeded_and_oversized_request_fails_alone():
+    clk = FakeClock()
+    ex = FakeExecutor(clk)
+    srv = Server(ex, hbm_budget_bytes=100, max_active=8, clock=clk, sleep=clk.sleep)
+    seen = []
+    orig = ex.step
+
+    def step(reqs):
+        seen.append(sum(r.inputs["bytes"] for r in reqs))
+        orig(reqs)
+
+    ex.step = step
+    reqs = srv.run(make([(0, 0.0, 2, 40), (1, 0.0, 2, 40), (2, 0.0, 2, 40), (3, 0.0, 1, 500)]))
+    assert max(seen) <= 100
+    st = {r.rid: r.status for r in reqs}
+    assert st == {0: "done", 1: "done", 2: "done", 3: "failed"}
+    assert "exceeds" in reqs[3].error
+
+
+def test_failed_admission_and_failed_tick_do_not_block_others():
+    clk = FakeClock()
+    ex = FakeExecutor(clk, fail_admit={1}, fail_step_at=2)
+    srv = Server(ex, hbm_budget_bytes=1000, max_active=4, clock=clk, sleep=clk.sleep)
+    reqs = srv.run(make([(0, 0.0, 3, 10), (1, 0.0, 3, 10), (2, 5.0, 2, 10)]))
+    st = {r.rid: r.status for r in reqs}
+    assert st[1] == "failed" and "admit" in reqs[1].error
+    assert st[0] == "failed" and "step" in reqs[0].error   # the second tick failed
+    assert st[2] == "done"                                 # a later request still runs
+    assert srv.used == 0
+
+
+def test_idle_server_waits_for_arrivals():
+    clk = FakeClock()
+    ex = FakeExecutor(clk, tick=0.01)
+    srv = Server(ex, 100, 4, clock=clk, sleep=clk.sleep)
+    reqs = srv.run(make([(0, 3.0, 1, 1)]))
+    assert reqs[0].t_admit >= 3.0 and reqs[0].status == "done"
+
+
+def test_poisson_stream_is_seeded():
+    a = poisson_requests(64, 2.0, 40, 30)
+    b = poisson_requests(64, 2.0, 40, 30)
+    assert a == b
+    arr = [x[1] for x in a]
+    assert arr[0] == 0.0 and all(y >= x for x, y in zip(arr, arr[1:]))
+    # mean inter-arrival close to 1 / rate
+    assert abs((arr[-1] / 63) - 0.5) < 0.2
+    assert {x[2] for x in a} == {"serve128", "serve256", "serve384"}
