@@ -31,6 +31,12 @@ FLOPS_FWD = 23
 FLOPS_VJP = 66
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (published)
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch of the dominant kernel, from the FETCH_SIZE / WRITE_SIZE counters of
+# two rocprofv3 --pmc runs of this script, scaled by the same counters read for a plain
+# elementwise kernel of known size (--copy-calib-mib). Valid only for the kernel source the
+# counters were taken on: the file records its hash, and traffic is null when it differs.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bp_vjp_head256_traffic.md")
+KERNEL_SOURCES = ("paper_2401_09283_amd/csrc/backproject.hip", "paper_2401_09283_amd/csrc/gmc_internal.hpp")
 
 
 def percentile(xs, q):
@@ -41,6 +47,45 @@ def percentile(xs, q):
     f = int(k)
     c = min(f + 1, len(xs) - 1)
     return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(config):
+    """Counter-derived HBM bytes per VJP launch recorded for this configuration and the
+    current kernel source, else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = [ln for ln in fh if ln.startswith("TRAFFIC ")]
+    except OSError:
+        return None
+    for ln in lines:
+        rec = json.loads(ln[len("TRAFFIC "):])
+        if rec.get("config") == config and rec.get("kernel_sha") == kernel_source_hash():
+            return rec
+    return None
+
+
+def copy_calibration(mib):
+    """One plain elementwise kernel (negation) over mib MiB of FP32: reads and writes exactly
+    mib MiB, the reference against which the HBM counters are scaled."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def cpu_baseline(case, n_views_sample):
@@ -80,6 +125,8 @@ def main():
     ap.add_argument("--lr", type=float, default=0.05)
     ap.add_argument("--cpu-views", type=int, default=16, help="views of the oracle's bounded CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one elementwise kernel over this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -103,6 +150,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    torch.cuda.reset_peak_memory_stats(dev)
+    if args.copy_calib_mib > 0:
+        copy_calibration(args.copy_calib_mib)
     bp = Backprojector.from_case(case, device=dev)
     proj = torch.from_numpy(case.proj).to(dev)
     solver = MotionSolver(bp, proj, SolverConfig(n_nodes=cfg.n_nodes, lr=args.lr, loss="entropy_tv"))
@@ -137,6 +187,7 @@ def main():
     upd = cfg.updates
     fwd_ms, vjp_ms = float(np.mean(t_fwd)), float(np.mean(t_vjp))
     achieved = FLOPS_VJP * upd / (vjp_ms * 1e-3) / 1e12
+    traffic = recorded_traffic(args.config)
     out = {
         "metric": METRIC,
         "value": upd / (ms_step * 1e-3) / 1e9,
@@ -164,7 +215,8 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": traffic["bytes"] if traffic else None,
+            "traffic_unit": "bytes per launch (HBM read + write)",
             "flops_per_update": FLOPS_VJP,
             "avg_launch_ms": vjp_ms,
         },
@@ -177,6 +229,7 @@ def main():
             "forward_tflops": FLOPS_FWD * upd / (fwd_ms * 1e-3) / 1e12,
         },
         "latency_ms": {"step_p50": percentile(t_stp, 50), "step_p99": percentile(t_stp, 99)},
+        "peak_hbm_gb": torch.cuda.max_memory_allocated() / 1e9,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
