@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
 #include <new>
 #include <string>
 #include <vector>
@@ -56,12 +57,13 @@ gmc_status validate_geometry(const gmc_geometry* g) {
 }
 
 // Same tile rule as k_setup, on the host and for the nominal matrices: the largest tile.
-void nominal_tile_extent(const gmc_plan* p, const double* P, int* tw_max, int* th_max) {
+// Tile extents (columns, rows) of the nominal (motion-free) geometry for every brick whose tile
+// meets the detector: every view for short scans, a subsample of long ones (a sizing
+// heuristic: a tile that exceeds the chosen LDS tile at run time is sampled from global memory
+// instead).
+void nominal_tile_extents(const gmc_plan* p, const double* P, std::vector<std::pair<int, int>>& out) {
     const gmc_geometry& g = p->g;
-    int twm = 0, thm = 0;
     const double ext[3] = {(BXY - 1) * g.voxel_mm[0], (BXY - 1) * g.voxel_mm[1], (p->bz - 1) * g.voxel_mm[2]};
-    // every view for short scans, a subsample of long ones (a sizing heuristic: a tile that
-    // exceeds the chosen LDS tile at run time is sampled from global memory instead)
     const int vstride = std::max(1, g.n_views / 128);
     for (int v = 0; v < g.n_views; v += vstride) {
         const double* Ph = P + 12 * v;
@@ -87,12 +89,25 @@ void nominal_tile_extent(const gmc_plan* p, const double* P, int* tw_max, int* t
             const int th = (int)(floor(vmax) + 1.0 - floor(vmin)) + 5;
             const int ou = (int)floor(umin) - 2, ov = (int)floor(vmin) - 2;
             if (ou + tw <= 0 || ou >= g.det_w || ov + th <= 0 || ov >= g.det_h) continue;
-            twm = std::max(twm, tw);
-            thm = std::max(thm, th);
+            out.emplace_back(tw, th);
         }
     }
-    *tw_max = twm;
-    *th_max = thm;
+}
+
+// The smallest tile configuration that holds at least 99 % of the nominal tiles with two
+// columns and rows to spare for motion (a smaller LDS tile fits more workgroups per CU; the
+// rest are sampled from global memory).
+int choose_tile_cfg(const gmc_plan* p, const double* P) {
+    std::vector<std::pair<int, int>> ext;
+    nominal_tile_extents(p, P, ext);
+    if (ext.empty()) return 0;
+    for (int c = 0; c < N_TILE_CFGS; ++c) {
+        size_t fit = 0;
+        for (const auto& e : ext)
+            if (e.first + 2 <= TILE_CFGS[c].tp && e.second + 2 <= TILE_CFGS[c].th) ++fit;
+        if (fit >= (size_t)(0.99 * (double)ext.size())) return c;
+    }
+    return N_TILE_CFGS - 1;
 }
 
 struct WS {
@@ -195,17 +210,7 @@ gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_p
                 delete p;
                 return fail(GMC_E_INVALID, "P_nominal has a non-finite entry");
             }
-        int twm, thm;
-        nominal_tile_extent(p, P_nominal, &twm, &thm);
-        // room for moderate motion: 4 extra columns and rows
-        twm += 4;
-        thm += 4;
-        p->tile_cfg = N_TILE_CFGS - 1;
-        for (int c = 0; c < N_TILE_CFGS; ++c)
-            if (TILE_CFGS[c].tp >= twm && TILE_CFGS[c].th >= thm) {
-                p->tile_cfg = c;
-                break;
-            }
+        p->tile_cfg = choose_tile_cfg(p, P_nominal);
     }
     const size_t n = (size_t)g->n_views;
     size_t off = 0;

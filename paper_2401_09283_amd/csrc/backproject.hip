@@ -90,42 +90,45 @@ __device__ __forceinline__ void fetch_global(const float* __restrict__ img, int 
 
 // ---------------------------------------------------------------- per-sample arithmetic
 
-// Homogeneous position of sample k of the thread's column, in the tile frame: identical in
-// every path (and in k_debug_project) so that every path sees the same detector position.
-struct Pos {
-    float uh, vh, rw, au, av;
-    float fu, fv;   // floor(uh), floor(vh): cell relative to the tile origin
+// Homogeneous position of sample k of the thread's column, in the tile frame, and its
+// reciprocal depth: identical in every path (and in k_debug_project), so that every path
+// sees the same detector position.
+struct Smp {
+    float rw, uh, vh;
 };
 
-__device__ __forceinline__ Pos sample_pos(float ub, float vb, float wb, float du, float dv, float dw, int k) {
+__device__ __forceinline__ Smp project(float ub, float vb, float wb, float du, float dv, float dw, int k) {
     const float kf = (float)k;
-    const float u = fmaf(kf, du, ub), vv = fmaf(kf, dv, vb), w = fmaf(kf, dw, wb);
-    Pos p;
-    p.rw = __builtin_amdgcn_rcpf(w);
-    p.uh = u * p.rw;
-    p.vh = vv * p.rw;
-    p.fu = floorf(p.uh);
-    p.fv = floorf(p.vh);
-    p.au = p.uh - p.fu;
-    p.av = p.vh - p.fv;
-    return p;
+    Smp s;
+    s.rw = __builtin_amdgcn_rcpf(fmaf(kf, dw, wb));
+    s.uh = fmaf(kf, du, ub) * s.rw;
+    s.vh = fmaf(kf, dv, vb) * s.rw;
+    return s;
 }
 
-// Linear LDS index of the sample's cell, clamped into the tile (a guard: the tile bounds
-// already contain every sample). Integer-valued floats keep it to med3 + one FMA + one cvt.
+// Cell and fraction of a tile coordinate. Every sample of a tile has positive tile
+// coordinates (the tile origin lies two pixels below the smallest projected brick corner),
+// so truncation is the floor and fract() is the bilinear weight.
+__device__ __forceinline__ int cell_of(float x) { return (int)x; }
+__device__ __forceinline__ float frac_of(float x) { return __builtin_amdgcn_fractf(x); }
+
+// Linear LDS index of the sample's cell (row-major, pitch TP), clamped into [lo, hi] so that
+// every tap stays inside the tile buffer (a guard: the tile bounds already contain every
+// sample). 24-bit multiply-add, one med3.
 template <int TP>
-__device__ __forceinline__ int tile_index(const Pos& p, float cmax, float rmax) {
-    const float cu = __builtin_amdgcn_fmed3f(p.fu, 1.0f, cmax);
-    const float cv = __builtin_amdgcn_fmed3f(p.fv, 1.0f, rmax);
-    return (int)fmaf(cv, (float)TP, cu);
+__device__ __forceinline__ int tile_cell(const Smp& s, int lo, int hi) {
+    const int L = (int)__umul24((unsigned)cell_of(s.vh), (unsigned)TP) + cell_of(s.uh);
+    return min(max(L, lo), hi);
 }
 
 // Row coefficients of Eq. 4 for one sample, accumulated into the 6 running sums of the column:
 // A = (g_u, g_v, g_u uh + g_v vh [+ 2 val]) * seed / w (Eq. 3 weighting) or * seed / w^3 (FDK).
 // gu, gv are doubled central differences and the seed is halved (paper gradient), or exact
-// bilinear derivatives with an unscaled seed (exact gradient).
+// bilinear derivatives with an unscaled seed (exact gradient). Samples arrive in decreasing k;
+// T_r += S_r after every sample with k > 0 makes T_r = sum_k k A_r(k) (suffix sums), the
+// z-moment of the column.
 template <int WEIGHT, int GRAD>
-__device__ __forceinline__ void accumulate(const Pos& p, float seed, float val, float gu, float gv, int k,
+__device__ __forceinline__ void accumulate(const Smp& p, float seed, float val, float gu, float gv, int k,
                                            float& S0, float& S1, float& S2, float& T0, float& T1, float& T2) {
     float e, tt;
     if (WEIGHT == GMC_WEIGHT_FDK) {
@@ -135,13 +138,14 @@ __device__ __forceinline__ void accumulate(const Pos& p, float seed, float val, 
         e = seed * p.rw;
         tt = fmaf(gu, p.uh, gv * p.vh);
     }
-    const float ek = e * (float)k;
     S0 = fmaf(e, gu, S0);
     S1 = fmaf(e, gv, S1);
     S2 = fmaf(e, tt, S2);
-    T0 = fmaf(ek, gu, T0);
-    T1 = fmaf(ek, gv, T1);
-    T2 = fmaf(ek, tt, T2);
+    if (k > 0) {
+        T0 += S0;
+        T1 += S1;
+        T2 += S2;
+    }
 }
 
 __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
@@ -179,6 +183,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                                          float* __restrict__ sRed) {
     constexpr int PLANE = TP * TH;
     constexpr int NSEG = (TP + 63) / 64;
+    static_assert(BZ % 8 == 0, "the forward samples a column in groups of 8");
     const int bj = brick % a.nby;
     const int bi = (brick / a.nby) % a.nbx;
     const int bk = brick / (a.nby * a.nbx);
@@ -210,29 +215,37 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
     ConstDesc* descs = (ConstDesc*)(desc + brick);
     const long long dstride = a.n_bricks;
 
-    // issue view vv's tile loads into buffer buf (asynchronous, no registers). Rows are
-    // distributed over the four waves; the row loop runs on scalar registers, each lane
-    // carries one (clamped) detector column per 64-column segment.
+    // Issue view vv's tile loads into buffer buf (asynchronous, no registers). Rows are
+    // distributed over the four waves and walked with scalar registers; each lane carries one
+    // clamped detector column per 64-column segment. A lane whose column lies past the tile
+    // width but inside the row pitch loads a clamped column there (unused); lanes past the
+    // pitch are masked once per segment. Interior tiles need no row clamp and step their row
+    // address by four rows.
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     auto stage = [&](const BrickDesc& D, int vv, int buf) {
         if (D.mode != TILE_INTERIOR && D.mode != TILE_EDGE) return;
         const float* __restrict__ img = proj + (long long)vv * a.plane;
         float* tile = sT + buf * PLANE;
         const int tw = D.tw, th = D.th;
-        int coff[NSEG];
-        bool cok[NSEG];
 #pragma unroll
         for (int q = 0; q < NSEG; ++q) {
+            if (q * 64 >= tw) break;
             const int c = q * 64 + lane;
-            coff[q] = min(max(D.ou + c, 0), a.W - 1);
-            cok[q] = c < tw;
-        }
-        for (int r = wv; r < th; r += 4) {
-            const int gr = min(max(D.ov + r, 0), a.H - 1);
-            const float* row = img + (long long)gr * a.W;
-#pragma unroll
-            for (int q = 0; q < NSEG; ++q)
-                if (cok[q]) __builtin_amdgcn_global_load_lds(row + coff[q], tile + r * TP + q * 64, 4, 0, 0);
+            const unsigned cb = 4u * (unsigned)min(max(D.ou + c, 0), a.W - 1);
+            if (q * 64 + 64 <= TP || c < TP) {
+                if (D.mode == TILE_INTERIOR) {
+                    const char* row = (const char*)(img + (long long)(D.ov + wv) * a.W);
+                    const long long step = 16LL * a.W;
+                    for (int r = wv; r < th; r += 4, row += step)
+                        __builtin_amdgcn_global_load_lds((const float*)(row + cb), tile + r * TP + q * 64, 4, 0, 0);
+                } else {
+                    for (int r = wv; r < th; r += 4) {
+                        const int gr = min(max(D.ov + r, 0), a.H - 1);
+                        const char* row = (const char*)(img + (long long)gr * a.W);
+                        __builtin_amdgcn_global_load_lds((const float*)(row + cb), tile + r * TP + q * 64, 4, 0, 0);
+                    }
+                }
+            }
         }
         if (D.mode == TILE_EDGE) {
             if (t < TP) {
@@ -281,81 +294,90 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
         const float wb = fmaf(m[8], qx, fmaf(m[9], qy, m[11]));
         const float du = m[2] * dz, dv = m[6] * dz, dw = m[10] * dz;
         const float* tile = sT + buf * PLANE;
-        const float cmax = (float)(cur.tw - 3), rmax = (float)(cur.th - 3);
+        const int cmax = cur.tw - 3, rmax = cur.th - 3;
 
         if (cur.mode == TILE_INTERIOR) {
-            // taps addressed from (row - 1, column - 1), so that every LDS offset is positive
-            const float* tile_m = tile - (TP + 1);
+            // cell (r, c) with 1 <= r <= rmax, 1 <= c <= cmax: every tap, halo included, in the tile
+            const int lo = TP + 1, hi = rmax * TP + cmax;
             if (!VJP) {
-                // positions of all samples first, then all LDS reads, then the arithmetic:
-                // the reads of one column are in flight together
-                int idx[BZ];
-                float au[BZ], av[BZ], ww[BZ];
+                // per group of 8 samples: positions first, then all LDS reads, then the
+                // arithmetic, so that the reads of a group are in flight together
 #pragma unroll
-                for (int k = 0; k < BZ; ++k) {
-                    const Pos p = sample_pos(ub, vb, wb, du, dv, dw, k);
-                    idx[k] = tile_index<TP>(p, cmax, rmax);
-                    au[k] = p.au;
-                    av[k] = p.av;
-                    ww[k] = (WEIGHT == GMC_WEIGHT_FDK) ? p.rw * p.rw : 1.0f;
-                }
-                float d00[BZ], d01[BZ], d10[BZ], d11[BZ];
+                for (int g = 0; g < BZ; g += 8) {
+                    int off[8];
+                    float au[8], av[8], ww[8];
 #pragma unroll
-                for (int k = 0; k < BZ; ++k) {
-                    const float* b = tile_m + idx[k] + TP + 1;
-                    d00[k] = b[0];
-                    d01[k] = b[1];
-                    d10[k] = b[TP];
-                    d11[k] = b[TP + 1];
-                }
+                    for (int k = 0; k < 8; ++k) {
+                        const Smp p = project(ub, vb, wb, du, dv, dw, g + k);
+                        off[k] = tile_cell<TP>(p, lo, hi);
+                        au[k] = frac_of(p.uh);
+                        av[k] = frac_of(p.vh);
+                        ww[k] = (WEIGHT == GMC_WEIGHT_FDK) ? p.rw * p.rw : 1.0f;
+                    }
+                    float d00[8], d01[8], d10[8], d11[8];
 #pragma unroll
-                for (int k = 0; k < BZ; ++k) {
-                    const float top = fmaf(au[k], d01[k] - d00[k], d00[k]);
-                    const float bot = fmaf(au[k], d11[k] - d10[k], d10[k]);
-                    const float val = fmaf(av[k], bot - top, top);
-                    acc[k] = (WEIGHT == GMC_WEIGHT_FDK) ? fmaf(val, ww[k], acc[k]) : acc[k] + val;
+                    for (int k = 0; k < 8; ++k) {
+                        const float* b = tile + off[k];
+                        d00[k] = b[0];
+                        d01[k] = b[1];
+                        d10[k] = b[TP];
+                        d11[k] = b[TP + 1];
+                    }
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const float top = lerp(d00[k], d01[k], au[k]);
+                        const float bot = lerp(d10[k], d11[k], au[k]);
+                        const float val = lerp(top, bot, av[k]);
+                        acc[g + k] = (WEIGHT == GMC_WEIGHT_FDK) ? fmaf(val, ww[k], acc[g + k]) : acc[g + k] + val;
+                    }
                 }
             } else {
+                // taps addressed from (row - 1, column - 1), so that every LDS offset is positive
+                const float* tile_m = tile - (TP + 1);
 #pragma unroll
-            for (int k = 0; k < BZ; ++k) {
-                const Pos p = sample_pos(ub, vb, wb, du, dv, dw, k);
-                const float* q = tile_m + tile_index<TP>(p, cmax, rmax);
-                const float* b = q + TP + 1;
-                const float d00 = b[0], d01 = b[1], d10 = b[TP], d11 = b[TP + 1];
-                const float e0 = d01 - d00, e1 = d11 - d10;
-                const float top = fmaf(p.au, e0, d00), bot = fmaf(p.au, e1, d10);
-                const float dtb = bot - top;
-                const float val = fmaf(p.av, dtb, top);
-                float gu, gv;
-                if (GRAD == GMC_GRAD_PAPER) {
-                    const float bm = q[TP], b2 = q[TP + 3], cm = q[2 * TP], c2 = q[2 * TP + 3];
-                    const float a0 = q[1], a1 = q[2], f0 = q[3 * TP + 1], f1 = q[3 * TP + 2];
-                    // doubled central differences at the four taps, interpolated bilinearly;
-                    // along v the rows are interpolated first: rows r0-1 and r0+2 give
-                    // (1-b)(row(r0+1) - row(r0-1)) + b (row(r0+2) - row(r0))
-                    gu = lerp(lerp(d01 - bm, b2 - d00, p.au), lerp(d11 - cm, c2 - d10, p.au), p.av);
-                    gv = lerp(bot - lerp(a0, a1, p.au), lerp(f0, f1, p.au) - top, p.av);
-                } else {
-                    gu = fmaf(p.av, e1 - e0, e0);
-                    gv = dtb;
+                for (int kk = 0; kk < BZ; ++kk) {
+                    const int k = BZ - 1 - kk;
+                    const Smp p = project(ub, vb, wb, du, dv, dw, k);
+                    const float au = frac_of(p.uh), av = frac_of(p.vh);
+                    const float* q = tile_m + tile_cell<TP>(p, lo, hi);
+                    const float* b = q + TP + 1;
+                    const float d00 = b[0], d01 = b[1], d10 = b[TP], d11 = b[TP + 1];
+                    const float e0 = d01 - d00, e1 = d11 - d10;
+                    const float top = fmaf(au, e0, d00), bot = fmaf(au, e1, d10);
+                    const float dtb = bot - top;
+                    const float val = fmaf(av, dtb, top);
+                    float gu, gv;
+                    if (GRAD == GMC_GRAD_PAPER) {
+                        const float bm = q[TP], b2 = q[TP + 3], cm = q[2 * TP], c2 = q[2 * TP + 3];
+                        const float a0 = q[1], a1 = q[2], f0 = q[3 * TP + 1], f1 = q[3 * TP + 2];
+                        // doubled central differences at the four taps, interpolated bilinearly;
+                        // along v the rows are interpolated first: rows r0-1 and r0+2 give
+                        // (1-b)(row(r0+1) - row(r0-1)) + b (row(r0+2) - row(r0))
+                        gu = lerp(lerp(d01 - bm, b2 - d00, au), lerp(d11 - cm, c2 - d10, au), av);
+                        gv = lerp(bot - lerp(a0, a1, au), lerp(f0, f1, au) - top, av);
+                    } else {
+                        gu = fmaf(av, e1 - e0, e0);
+                        gv = dtb;
+                    }
+                    accumulate<WEIGHT, GRAD>(p, seed[k], val, gu, gv, k, S0, S1, S2, T0, T1, T2);
                 }
-                accumulate<WEIGHT, GRAD>(p, seed[k], val, gu, gv, k, S0, S1, S2, T0, T1, T2);
-            }
             }
         } else if (cur.mode == TILE_EDGE) {
             const float2* ct = sCol + buf * TP;
             const float2* rt = sRow + buf * TH;
 #pragma unroll
-            for (int k = 0; k < BZ; ++k) {
-                const Pos p = sample_pos(ub, vb, wb, du, dv, dw, k);
-                const int ci = (int)__builtin_amdgcn_fmed3f(p.fu, 1.0f, cmax);
-                const int ri = (int)__builtin_amdgcn_fmed3f(p.fv, 1.0f, rmax);
+            for (int kk = 0; kk < BZ; ++kk) {
+                const int k = VJP ? BZ - 1 - kk : kk;
+                const Smp p = project(ub, vb, wb, du, dv, dw, k);
+                const float au = frac_of(p.uh), av = frac_of(p.vh);
+                const int ci = min(max(cell_of(p.uh), 1), cmax);
+                const int ri = min(max(cell_of(p.vh), 1), rmax);
                 const float* b = tile + ri * TP + ci;
                 const float2 c0 = ct[ci], c1 = ct[ci + 1], r0 = rt[ri], r1 = rt[ri + 1];
                 const float d00 = b[0], d01 = b[1], d10 = b[TP], d11 = b[TP + 1];
-                const float u0 = 1.0f - p.au, v0 = 1.0f - p.av;
+                const float u0 = 1.0f - au, v0 = 1.0f - av;
                 // bilinear weights with the outside taps masked (z)
-                const float wc0 = u0 * c0.x, wc1 = p.au * c1.x, wr0 = v0 * r0.x, wr1 = p.av * r1.x;
+                const float wc0 = u0 * c0.x, wc1 = au * c1.x, wr0 = v0 * r0.x, wr1 = av * r1.x;
                 const float val = fmaf(wr0, fmaf(wc0, d00, wc1 * d01), wr1 * fmaf(wc0, d10, wc1 * d11));
                 if (!VJP) {
                     acc[k] += (WEIGHT == GMC_WEIGHT_FDK) ? val * (p.rw * p.rw) : val;
@@ -365,7 +387,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                         const float bm = b[-1], b2 = b[2], cm = b[TP - 1], c2 = b[TP + 2];
                         const float a0 = b[-TP], a1 = b[-TP + 1], f0 = b[2 * TP], f1 = b[2 * TP + 1];
                         // g_u: one-sided factor s per column, rows masked; g_v: s per row, columns masked
-                        const float sc0 = u0 * c0.y, sc1 = p.au * c1.y, sr0 = v0 * r0.y, sr1 = p.av * r1.y;
+                        const float sc0 = u0 * c0.y, sc1 = au * c1.y, sr0 = v0 * r0.y, sr1 = av * r1.y;
                         gu = fmaf(wr0, fmaf(sc0, d01 - bm, sc1 * (b2 - d00)), wr1 * fmaf(sc0, d11 - cm, sc1 * (c2 - d10)));
                         gv = fmaf(sr0, fmaf(wc0, d10 - a0, wc1 * (d11 - a1)), sr1 * fmaf(wc0, f0 - d00, wc1 * (f1 - d01)));
                     } else {
@@ -379,30 +401,33 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
         } else if (cur.mode == TILE_GLOBAL) {
             const float* __restrict__ img = proj + (long long)v * a.plane;
 #pragma unroll 1
-            for (int k = 0; k < BZ; ++k) {
-                const Pos p = sample_pos(ub, vb, wb, du, dv, dw, k);
+            for (int kk = 0; kk < BZ; ++kk) {
+                const int k = VJP ? BZ - 1 - kk : kk;
+                const Smp p = project(ub, vb, wb, du, dv, dw, k);
+                const float au = frac_of(p.uh), av = frac_of(p.vh);
                 Taps tp;
-                fetch_global<VJP && GRAD == GMC_GRAD_PAPER>(img, a.W, a.H, (int)p.fv + cur.ov, (int)p.fu + cur.ou, tp);
+                fetch_global<VJP && GRAD == GMC_GRAD_PAPER>(img, a.W, a.H, cell_of(p.vh) + cur.ov, cell_of(p.uh) + cur.ou,
+                                                            tp);
                 const float e0 = tp.d01 - tp.d00, e1 = tp.d11 - tp.d10;
-                const float top = fmaf(p.au, e0, tp.d00), bot = fmaf(p.au, e1, tp.d10);
+                const float top = fmaf(au, e0, tp.d00), bot = fmaf(au, e1, tp.d10);
                 const float dtb = bot - top;
-                const float val = fmaf(p.av, dtb, top);
+                const float val = fmaf(av, dtb, top);
                 // acc / seed are indexed dynamically here (this path is rare): select by k
 #pragma unroll
-                for (int kk = 0; kk < BZ; ++kk) {
-                    if (kk != k) continue;
+                for (int k2 = 0; k2 < BZ; ++k2) {
+                    if (k2 != k) continue;
                     if (!VJP) {
-                        acc[kk] += (WEIGHT == GMC_WEIGHT_FDK) ? val * (p.rw * p.rw) : val;
+                        acc[k2] += (WEIGHT == GMC_WEIGHT_FDK) ? val * (p.rw * p.rw) : val;
                     } else {
                         float gu, gv;
                         if (GRAD == GMC_GRAD_PAPER) {
-                            gu = lerp(lerp(tp.u00, tp.u01, p.au), lerp(tp.u10, tp.u11, p.au), p.av);
-                            gv = lerp(lerp(tp.v00, tp.v01, p.au), lerp(tp.v10, tp.v11, p.au), p.av);
+                            gu = lerp(lerp(tp.u00, tp.u01, au), lerp(tp.u10, tp.u11, au), av);
+                            gv = lerp(lerp(tp.v00, tp.v01, au), lerp(tp.v10, tp.v11, au), av);
                         } else {
-                            gu = fmaf(p.av, e1 - e0, e0);
+                            gu = fmaf(av, e1 - e0, e0);
                             gv = dtb;
                         }
-                        accumulate<WEIGHT, GRAD>(p, seed[kk], val, gu, gv, kk, S0, S1, S2, T0, T1, T2);
+                        accumulate<WEIGHT, GRAD>(p, seed[k2], val, gu, gv, k2, S0, S1, S2, T0, T1, T2);
                     }
                 }
             }
@@ -452,8 +477,11 @@ struct BpShared {
     float sRed[2 * 4 * 12];
 };
 
+// workgroups per CU the register budget is sized for: as many as the LDS tile allows, up to 4
+constexpr int bp_occupancy(int plane) { return plane <= 72 * 64 ? 4 : 2; }
+
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
-__global__ void __launch_bounds__(THREADS, 3)
+__global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH))
     k_bp(BpArgs a, const BrickDesc* __restrict__ desc, const float* __restrict__ proj, float* __restrict__ vol,
          const float* __restrict__ gvol, float* __restrict__ part) {
     __shared__ BpShared<TP, TH> sh;
@@ -466,7 +494,7 @@ __global__ void __launch_bounds__(THREADS, 3)
 // Several plans in one launch: the bricks of all items form one index space (item q owns
 // [begin_q, begin_q + n_bricks_q)), mapped to XCDs like a single plan's bricks.
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
-__global__ void __launch_bounds__(THREADS, 3) k_bp_batch(BatchTable tab) {
+__global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH)) k_bp_batch(BatchTable tab) {
     __shared__ BpShared<TP, TH> sh;
     const int blk = blockIdx.x;
     const int g = (blk & 7) * tab.per_xcd + (blk >> 3);
@@ -571,11 +599,11 @@ __global__ void k_debug_project(const BrickDesc* __restrict__ desc, int n_bricks
     const float vb = fmaf(D.m[4], qx, fmaf(D.m[5], qy, D.m[7]));
     const float wb = fmaf(D.m[8], qx, fmaf(D.m[9], qy, D.m[11]));
     const float du = D.m[2] * dz, dv = D.m[6] * dz, dw = D.m[10] * dz;
-    const Pos p = sample_pos(ub, vb, wb, du, dv, dw, kk);
-    cell[2 * q] = (int)p.fu + D.ou;
-    cell[2 * q + 1] = (int)p.fv + D.ov;
-    frac[2 * q] = p.au;
-    frac[2 * q + 1] = p.av;
+    const Smp p = project(ub, vb, wb, du, dv, dw, kk);
+    cell[2 * q] = cell_of(p.uh) + D.ou;
+    cell[2 * q + 1] = cell_of(p.vh) + D.ov;
+    frac[2 * q] = frac_of(p.uh);
+    frac[2 * q + 1] = frac_of(p.vh);
 }
 
 hipError_t launch_debug_project(const gmc_plan* p, const BrickDesc* desc, long long n, const int64_t* voxel,

@@ -36,11 +36,15 @@ static_assert(sizeof(BrickDesc) == 64, "descriptor must be 64 bytes");
 // the tile origin (ou, ov) as int bits, then 2 unused slots.
 constexpr int PART_STRIDE = 16;
 
-// Tile configurations (pitch TP floats, TH rows per plane) compiled into the kernels.
+// Tile configurations (pitch TP floats, TH rows per plane) compiled into the kernels. Two
+// planes of 72 x 64 floats plus the border tables fit four workgroups into the 160 KB of LDS
+// of a CU; a brick of 16^3 voxels at 1 mm in the 200-degree scan geometry projects to at most
+// about 74 x 63 pixels, and a tile that exceeds the plan's configuration is sampled from global
+// memory instead.
 struct TileCfg {
     int tp, th;
 };
-constexpr TileCfg TILE_CFGS[] = {{40, 40}, {80, 72}, {128, 96}};
+constexpr TileCfg TILE_CFGS[] = {{40, 40}, {72, 64}, {128, 96}};
 constexpr int TILE_CFG_MAX_TP = 128;
 constexpr int N_TILE_CFGS = 3;
 

@@ -64,7 +64,7 @@ def test_nominal_geometry_picks_the_tile():
     from synth import CONFIGS
     from synth.geometry import projection_matrices
 
-    for name, pitch in (("tiny", 40), ("head256", 80)):
+    for name, pitch in (("tiny", 40), ("head256", 72)):
         cfg = CONFIGS[name]
         g = gmc.make_geometry(cfg.n_views, cfg.det_w, cfg.det_h, cfg.grid.shape, cfg.grid.voxel_mm, cfg.grid.origin_mm)
         assert gmc.Plan(g, projection_matrices(cfg.scan)).info()["tile_pitch"] == pitch
