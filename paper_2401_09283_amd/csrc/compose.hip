@@ -99,8 +99,10 @@ __global__ void k_setup(SetupArgs a) {
     if (bad || !(umax - umin < 1e6) || !(vmax - vmin < 1e6)) {
         for (int e = 0; e < 12; ++e) d.m[e] = 0.0f;
         d.ou = d.ov = 0;
+        d.kin = d.kout = 0;
         d.tw = d.th = 0;
         d.mode = TILE_SKIP;
+        d.pad = 0;
         atomicOr(a.status, 1);
         a.desc[idx] = d;
         return;
@@ -137,8 +139,39 @@ __global__ void k_setup(SetupArgs a) {
     } else {
         d.mode = TILE_EDGE;
     }
-    d.tw = (int16_t)(tw < 32767 ? tw : 32767);
-    d.th = (int16_t)(th < 32767 ? th : 32767);
+    d.tw = (uint8_t)(tw < 255 ? tw : 255);
+    d.th = (uint8_t)(th < 255 ? th : 255);
+    d.pad = 0;
+    d.kin = d.kout = 0;
+    if (d.mode == TILE_EDGE) {
+        // Classify the brick's z-slices. At fixed z, u/w and v/w are linear-fractional in
+        // (x, y), so the four corners of a slice bound its projection. A slice whose tap cells
+        // (c, c+1) x (r, r+1) all satisfy 1 <= c, c+1 <= W-2, 1 <= r, r+1 <= H-2 needs no border
+        // rule (central differences stay inside); a slice whose tap cells all lie outside the
+        // detector contributes nothing (values and differences are 0 there). 1e-3 pixel of margin
+        // covers the FP32 positions of the sampling kernels.
+        const double eps = 1e-3;
+        for (int k = 0; k < a.bz && k < 16; ++k) {
+            const double z = o[2] + (double)k * a.dz;
+            double ulo = 1e300, uhi = -1e300, vlo = 1e300, vhi = -1e300;
+            bool ok = true;
+            for (int c = 0; c < 4; ++c) {
+                const double x = o[0] + ((c & 1) ? ext[0] : 0.0);
+                const double y = o[1] + ((c & 2) ? ext[1] : 0.0);
+                const double w = Ph[8] * x + Ph[9] * y + Ph[10] * z + Ph[11];
+                if (!(w > 0.0)) { ok = false; break; }
+                const double uh = (Ph[0] * x + Ph[1] * y + Ph[2] * z + Ph[3]) / w;
+                const double vh = (Ph[4] * x + Ph[5] * y + Ph[6] * z + Ph[7]) / w;
+                ulo = fmin(ulo, uh); uhi = fmax(uhi, uh);
+                vlo = fmin(vlo, vh); vhi = fmax(vhi, vh);
+            }
+            if (!ok) continue;
+            const double c0 = floor(ulo - eps), c1 = floor(uhi + eps) + 1.0;
+            const double r0 = floor(vlo - eps), r1 = floor(vhi + eps) + 1.0;
+            if (c0 >= 1.0 && c1 <= (double)(a.W - 2) && r0 >= 1.0 && r1 <= (double)(a.H - 2)) d.kin |= (uint16_t)(1u << k);
+            if (c1 < 0.0 || c0 > (double)(a.W - 1) || r1 < 0.0 || r0 > (double)(a.H - 1)) d.kout |= (uint16_t)(1u << k);
+        }
+    }
     a.desc[idx] = d;
 }
 

@@ -26,9 +26,13 @@ enum TileMode : int32_t {
 };
 struct BrickDesc {
     float m[12];
-    int32_t ou, ov;   // detector column / row of tile index 0
-    int16_t tw, th;   // tile extent (columns, rows)
-    int32_t mode;     // TileMode
+    int32_t ou, ov;       // detector column / row of tile index 0
+    uint16_t kin, kout;   // border tiles: bit k is set when every tap of the brick's slice k lies
+                          // inside the detector away from its border (plain formulas apply) /
+                          // outside the detector (the slice contributes nothing)
+    uint8_t tw, th;       // tile extent (columns, rows); 255 for tiles sampled from global memory
+    uint8_t mode;         // TileMode
+    uint8_t pad;
 };
 static_assert(sizeof(BrickDesc) == 64, "descriptor must be 64 bytes");
 
