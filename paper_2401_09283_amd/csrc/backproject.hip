@@ -128,6 +128,7 @@ __device__ __forceinline__ Smp next_sample(Column& c, int k) {
 // x + (2^23 - 1/2) rounds to 2^23 + floor(x) (to 2^23 + x - 1 when x is an integer; then the
 // fraction is 1 and the bilinear value is the same). Every sample of a tile has tile
 // coordinates >= 1 (the tile origin lies two pixels below the smallest projected corner).
+constexpr int VJP_GROUP = 1;          // VJP samples whose LDS reads are issued together
 constexpr float RND23 = 8388607.5f;   // 2^23 - 1/2
 constexpr float TWO23 = 8388608.0f;   // 2^23
 
@@ -199,31 +200,60 @@ __device__ __forceinline__ void accumulate(const Smp& p, float seed, float val, 
 
 __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
 
-// Taps of a sample whose taps, halo included, lie inside the detector (no border rule):
-// bilinear value and, for the VJP, the interpolated doubled central differences (paper
-// gradient) or the derivatives of the bilinear interpolant (exact gradient). q addresses the
-// tap at (row - 1, column - 1) of the sample's cell, so that every offset is positive.
+// Taps of a sample whose taps, halo included, lie inside the detector (no border rule): the
+// four bilinear taps and, for the paper gradient, the eight neighbours the central differences
+// need. q addresses the tap at (row - 1, column - 1) of the sample's cell, so that every offset
+// is positive.
+struct Taps12 {
+    float d00, d01, d10, d11;
+    float bm, b2, cm, c2, a0, a1, f0, f1;
+};
+
 template <int TP, int GRAD, bool GRADS>
-__device__ __forceinline__ void taps_plain(LdsF* q, float au, float av, float& val, float& gu, float& gv) {
+__device__ __forceinline__ void load_plain(LdsF* q, Taps12& t) {
     LdsF* b = q + TP + 1;
-    const float d00 = b[0], d01 = b[1], d10 = b[TP], d11 = b[TP + 1];
-    const float e0 = d01 - d00, e1 = d11 - d10;
-    const float top = fmaf(au, e0, d00), bot = fmaf(au, e1, d10);
+    t.d00 = b[0];
+    t.d01 = b[1];
+    t.d10 = b[TP];
+    t.d11 = b[TP + 1];
+    if (GRADS && GRAD == GMC_GRAD_PAPER) {
+        t.bm = q[TP];
+        t.b2 = q[TP + 3];
+        t.cm = q[2 * TP];
+        t.c2 = q[2 * TP + 3];
+        t.a0 = q[1];
+        t.a1 = q[2];
+        t.f0 = q[3 * TP + 1];
+        t.f1 = q[3 * TP + 2];
+    }
+}
+
+// Bilinear value and, for the VJP, the interpolated doubled central differences (paper
+// gradient) or the derivatives of the bilinear interpolant (exact gradient).
+template <int GRAD, bool GRADS>
+__device__ __forceinline__ void eval_plain(const Taps12& t, float au, float av, float& val, float& gu, float& gv) {
+    const float e0 = t.d01 - t.d00, e1 = t.d11 - t.d10;
+    const float top = fmaf(au, e0, t.d00), bot = fmaf(au, e1, t.d10);
     const float dtb = bot - top;
     val = fmaf(av, dtb, top);
     if (!GRADS) return;
     if (GRAD == GMC_GRAD_PAPER) {
-        const float bm = q[TP], b2 = q[TP + 3], cm = q[2 * TP], c2 = q[2 * TP + 3];
-        const float a0 = q[1], a1 = q[2], f0 = q[3 * TP + 1], f1 = q[3 * TP + 2];
         // doubled central differences at the four taps, interpolated bilinearly; along v the
         // rows are interpolated first: rows r0-1 and r0+2 give
         // (1-b)(row(r0+1) - row(r0-1)) + b (row(r0+2) - row(r0))
-        gu = lerp(lerp(d01 - bm, b2 - d00, au), lerp(d11 - cm, c2 - d10, au), av);
-        gv = lerp(bot - lerp(a0, a1, au), lerp(f0, f1, au) - top, av);
+        gu = lerp(lerp(t.d01 - t.bm, t.b2 - t.d00, au), lerp(t.d11 - t.cm, t.c2 - t.d10, au), av);
+        gv = lerp(bot - lerp(t.a0, t.a1, au), lerp(t.f0, t.f1, au) - top, av);
     } else {
         gu = fmaf(av, e1 - e0, e0);
         gv = dtb;
     }
+}
+
+template <int TP, int GRAD, bool GRADS>
+__device__ __forceinline__ void taps_plain(LdsF* q, float au, float av, float& val, float& gu, float& gv) {
+    Taps12 t;
+    load_plain<TP, GRAD, GRADS>(q, t);
+    eval_plain<GRAD, GRADS>(t, au, av, val, gu, gv);
 }
 
 // Taps of a sample near or across the detector border, masked with the border tables:
@@ -308,7 +338,23 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
     if (VJP) {
         const float sc = (GRAD == GMC_GRAD_PAPER) ? 0.5f : 1.0f;
 #pragma unroll
-        for (int k = 0; k < BZ; ++k) seed[k] = (col_in && k0 + k < a.nz) ? sc * gvol[col_off + k] : 0.0f;
+        for (int k = 0; k < BZ; ++k) seed[k] = 0.0f;
+        if (col_in && k0 + BZ <= a.nz && ((size_t)(gvol + col_off) & 15) == 0) {
+            // whole column inside the volume, 16-byte aligned: one vector load per 4 voxels
+            const float4* g4 = (const float4*)(gvol + col_off);
+#pragma unroll
+            for (int k4 = 0; k4 < BZ / 4; ++k4) {
+                const float4 x = g4[k4];
+                seed[4 * k4 + 0] = sc * x.x;
+                seed[4 * k4 + 1] = sc * x.y;
+                seed[4 * k4 + 2] = sc * x.z;
+                seed[4 * k4 + 3] = sc * x.w;
+            }
+        } else if (col_in) {
+#pragma unroll
+            for (int k = 0; k < BZ; ++k)
+                if (k0 + k < a.nz) seed[k] = sc * gvol[col_off + k];
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < BZ; ++k) acc[k] = 0.0f;
@@ -322,29 +368,29 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
 
     // Issue view vv's tile loads into buffer buf (asynchronous, no registers). Rows are
     // distributed over the four waves and walked with scalar registers; each lane carries one
-    // clamped detector column per 64-column segment. A lane whose column lies past the tile
-    // width but inside the row pitch loads a clamped column there (unused); lanes past the
-    // pitch are masked once per segment. Interior tiles need no row clamp and step their row
-    // address by four rows.
+    // clamped detector column per 64-column segment, lanes outside the tile's columns are masked
+    // once per segment. Interior tiles need no row clamp and step their row address by four rows.
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     auto stage = [&](const BrickDesc& D, int vv, int buf) {
         if (D.mode != TILE_INTERIOR && D.mode != TILE_EDGE) return;
         const float* __restrict__ img = proj + (long long)vv * a.plane;
         float* tile = sT + buf * PLANE;
-        const int tw = D.tw, th = D.th;
+        // the VJP needs the whole tile; the forward no halo: rows and columns 1 .. extent - 2
+        constexpr int H0 = VJP ? 0 : 1;
+        const int c_end = D.tw - H0, r_end = D.th - H0;
 #pragma unroll
         for (int q = 0; q < NSEG; ++q) {
-            if (q * 64 >= tw) break;
+            if (q * 64 >= c_end) break;
             const int c = q * 64 + lane;
             const unsigned cb = 4u * (unsigned)min(max(D.ou + c, 0), a.W - 1);
-            if (q * 64 + 64 <= TP || c < TP) {
+            if (c >= H0 && c < c_end) {   // lanes outside the tile's columns stay idle
                 if (D.mode == TILE_INTERIOR) {
-                    const char* row = (const char*)(img + (long long)(D.ov + wv) * a.W);
+                    const char* row = (const char*)(img + (long long)(D.ov + H0 + wv) * a.W);
                     const long long step = 16LL * a.W;
-                    for (int r = wv; r < th; r += 4, row += step)
+                    for (int r = H0 + wv; r < r_end; r += 4, row += step)
                         __builtin_amdgcn_global_load_lds((const float*)(row + cb), tile + r * TP + q * 64, 4, 0, 0);
                 } else {
-                    for (int r = wv; r < th; r += 4) {
+                    for (int r = H0 + wv; r < r_end; r += 4) {
                         const int gr = min(max(D.ov + r, 0), a.H - 1);
                         const char* row = (const char*)(img + (long long)gr * a.W);
                         __builtin_amdgcn_global_load_lds((const float*)(row + cb), tile + r * TP + q * 64, 4, 0, 0);
@@ -444,14 +490,26 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
             } else {
                 // taps addressed from (row - 1, column - 1), so that every LDS offset is positive
                 const unsigned base_m = base - 4u * (TP + 1);
+                // per group of VJP_GROUP samples: positions, then the LDS reads, then the arithmetic
 #pragma unroll
-                for (int k = 0; k < BZ; ++k) {
-                    const Smp p = next_sample(col, k);
-                    const Cell c = cell_of(p);
-                    const float au = c.au, av = c.av;
-                    float val, gu, gv;
-                    taps_plain<TP, GRAD, true>(lds_f(tile_cell<TP>(c, lo, hi, base_m)), au, av, val, gu, gv);
-                    accumulate<BZ, WEIGHT, GRAD>(p, seed[k], val, gu, gv, k, S0, S1, S2, T0, T1, T2);
+                for (int g = 0; g < BZ; g += VJP_GROUP) {
+                    Smp p[VJP_GROUP];
+                    Cell c[VJP_GROUP];
+                    Taps12 tp[VJP_GROUP];
+#pragma unroll
+                    for (int i = 0; i < VJP_GROUP; ++i) {
+                        p[i] = next_sample(col, g + i);
+                        c[i] = cell_of(p[i]);
+                    }
+#pragma unroll
+                    for (int i = 0; i < VJP_GROUP; ++i)
+                        load_plain<TP, GRAD, true>(lds_f(tile_cell<TP>(c[i], lo, hi, base_m)), tp[i]);
+#pragma unroll
+                    for (int i = 0; i < VJP_GROUP; ++i) {
+                        float val, gu, gv;
+                        eval_plain<GRAD, true>(tp[i], c[i].au, c[i].av, val, gu, gv);
+                        accumulate<BZ, WEIGHT, GRAD>(p[i], seed[g + i], val, gu, gv, g + i, S0, S1, S2, T0, T1, T2);
+                    }
                 }
             }
         } else if (cur.mode == TILE_EDGE) {
