@@ -193,7 +193,7 @@ gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_p
     gmc_plan* p = new (std::nothrow) gmc_plan();
     if (!p) return fail(GMC_E_INVALID, "out of host memory");
     p->g = *g;
-    p->bz = 16;
+    p->bz = BRICK_Z;
     p->nbx = (g->nx + BXY - 1) / BXY;
     p->nby = (g->ny + BXY - 1) / BXY;
     p->nbz = (g->nz + p->bz - 1) / p->bz;

@@ -2,14 +2,15 @@
 //
 // One workgroup of 256 threads owns a brick of 16 x 16 x BZ voxels; thread (li, lj) owns the
 // column of BZ voxels at (li, lj). For every view the workgroup stages the brick's detector
-// tile in LDS (the filtered projection with a one-pixel halo and, for the VJP, the two
-// central-difference images of Sec. II-B.2 computed from it), then every thread walks its
-// column: homogeneous position by FMA from the column base, one reciprocal, bilinear taps
-// from LDS. The forward pass accumulates its BZ voxels in registers over all views and
-// writes them once (z fastest). The VJP keeps the seed of its BZ voxels in registers, sums
-// the per-sample row coefficients of Eq. 4 (6 running sums per thread, since x and y are
-// constant along a column), reduces them over the workgroup with DPP at the end of each
-// view and writes one 12-entry partial per (view, brick); k_reduce_chain finishes the sum.
+// tile in LDS (the filtered projection, with a one-pixel halo for the central differences of
+// Sec. II-B.2, which are formed from the tile's taps on the fly), then every thread walks its
+// column: homogeneous position by FMA from the column base, one reciprocal per column and a
+// Newton step per sample, bilinear taps from LDS. The forward pass accumulates its BZ voxels
+// in registers over all views and writes them once (z fastest). The VJP keeps the seed of its
+// BZ voxels in registers, sums the per-sample row coefficients of Eq. 4 (6 running sums per
+// thread, since x and y are constant along a column), reduces them over the workgroup with
+// cross-lane permutes at the end of each view and writes one 12-entry partial per
+// (view, brick); k_reduce_chain finishes the sum.
 //
 // Workgroups are mapped to bricks so that each XCD (workgroup id mod 8) takes a contiguous
 // range of z-slabs: its L2 then holds only the detector rows those slabs project to.
@@ -635,8 +636,8 @@ struct BpShared {
     float sRed[2 * 4 * 12];
 };
 
-// workgroups per CU the register budget is sized for: as many as the LDS tile allows, up to 4
-constexpr int bp_occupancy(int plane) { return plane <= 72 * 64 ? 4 : 1; }
+// workgroups per CU the register budget is sized for: as many as the LDS tile allows
+constexpr int bp_occupancy(int plane) { return plane <= 80 * 36 ? 6 : (plane <= 128 * 64 ? 2 : 1); }
 
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
 __global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH))
@@ -715,19 +716,19 @@ hipError_t launch_batch_cfg(int W, int G, const BatchTable& tab, bool vjp, hipSt
 hipError_t launch_bp_batch(int tile_cfg, int weighting, int grad_mode, const BatchTable& tab, bool vjp, hipStream_t s) {
     if (tab.n < 1 || tab.n > MAX_BATCH || tab.total < 1) return hipErrorInvalidValue;
     switch (tile_cfg) {
-        case 0: return launch_batch_cfg<TILE_CFGS[0].tp, TILE_CFGS[0].th, 16>(weighting, grad_mode, tab, vjp, s);
-        case 1: return launch_batch_cfg<TILE_CFGS[1].tp, TILE_CFGS[1].th, 16>(weighting, grad_mode, tab, vjp, s);
-        case 2: return launch_batch_cfg<TILE_CFGS[2].tp, TILE_CFGS[2].th, 16>(weighting, grad_mode, tab, vjp, s);
+        case 0: return launch_batch_cfg<TILE_CFGS[0].tp, TILE_CFGS[0].th, BRICK_Z>(weighting, grad_mode, tab, vjp, s);
+        case 1: return launch_batch_cfg<TILE_CFGS[1].tp, TILE_CFGS[1].th, BRICK_Z>(weighting, grad_mode, tab, vjp, s);
+        case 2: return launch_batch_cfg<TILE_CFGS[2].tp, TILE_CFGS[2].th, BRICK_Z>(weighting, grad_mode, tab, vjp, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_bp(const gmc_plan* p, const BpArgs& a, bool vjp, hipStream_t s) {
-    if (p->bz != 16) return hipErrorInvalidValue;
+    if (p->bz != BRICK_Z) return hipErrorInvalidValue;
     switch (p->tile_cfg) {
-        case 0: return launch_cfg<TILE_CFGS[0].tp, TILE_CFGS[0].th, 16>(p, a, vjp, s);
-        case 1: return launch_cfg<TILE_CFGS[1].tp, TILE_CFGS[1].th, 16>(p, a, vjp, s);
-        case 2: return launch_cfg<TILE_CFGS[2].tp, TILE_CFGS[2].th, 16>(p, a, vjp, s);
+        case 0: return launch_cfg<TILE_CFGS[0].tp, TILE_CFGS[0].th, BRICK_Z>(p, a, vjp, s);
+        case 1: return launch_cfg<TILE_CFGS[1].tp, TILE_CFGS[1].th, BRICK_Z>(p, a, vjp, s);
+        case 2: return launch_cfg<TILE_CFGS[2].tp, TILE_CFGS[2].th, BRICK_Z>(p, a, vjp, s);
         default: return hipErrorInvalidValue;
     }
 }

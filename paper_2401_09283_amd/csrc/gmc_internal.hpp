@@ -9,9 +9,11 @@
 
 namespace gmc {
 
-// Voxel bricks are BXY x BXY columns of BZ voxels; one workgroup of BXY*BXY threads owns
-// a brick and each thread owns one column (a run of BZ voxels along z).
+// Voxel bricks are BXY x BXY columns of BRICK_Z voxels; one workgroup of BXY*BXY threads
+// owns a brick and each thread owns one column (a run of BRICK_Z voxels along z). Shallow
+// bricks keep the detector tile small (six workgroups per CU).
 constexpr int BXY = 16;
+constexpr int BRICK_Z = 8;
 constexpr int THREADS = BXY * BXY;
 
 // One per (view, brick), 64 bytes, read with scalar loads by the backprojection kernels.
@@ -41,14 +43,15 @@ static_assert(sizeof(BrickDesc) == 64, "descriptor must be 64 bytes");
 constexpr int PART_STRIDE = 16;
 
 // Tile configurations (pitch TP floats, TH rows per plane) compiled into the kernels. Two
-// planes of 72 x 64 floats plus the border tables fit four workgroups into the 160 KB of LDS
-// of a CU; a brick of 16^3 voxels at 1 mm in the 200-degree scan geometry projects to at most
-// about 74 x 63 pixels, and a tile that exceeds the plan's configuration is sampled from global
-// memory instead.
+// planes of 80 x 36 floats plus the border tables fit six workgroups into the 160 KB of LDS of
+// a CU; a brick of 16 x 16 x 8 voxels at 1 mm in the 200-degree scan geometry projects to at
+// most about 74 x 38 pixels, and a tile that exceeds the plan's configuration is sampled from
+// global memory instead. A row pitch of 80 floats (16 banks apart modulo 32) spreads the
+// neighbouring rows a wavefront reads over different LDS banks.
 struct TileCfg {
     int tp, th;
 };
-constexpr TileCfg TILE_CFGS[] = {{40, 40}, {72, 64}, {128, 96}};
+constexpr TileCfg TILE_CFGS[] = {{40, 40}, {80, 36}, {128, 64}};
 constexpr int TILE_CFG_MAX_TP = 128;
 constexpr int N_TILE_CFGS = 3;
 

@@ -52,9 +52,9 @@ def test_invalid_geometry_is_rejected(bad):
 def test_plan_bricks_and_workspace():
     p = gmc.Plan(_geom())
     info = p.info()
-    assert info["brick"] == (16, 16, 16)
-    assert info["n_bricks"] == 2 * 2 * 2           # ragged: 20, 18, 17 -> 2 bricks per axis
-    n, nb = 10, 8
+    assert info["brick"] == (16, 16, 8)
+    assert info["n_bricks"] == 2 * 2 * 3           # ragged: 20, 18, 17 -> 2, 2 and 3 bricks
+    n, nb = 10, 12
     # at least: Phat + dPhat + descriptors (64 B) + partials (64 B) per (view, brick)
     assert p.workspace_bytes >= n * 12 * 8 + n * 72 * 8 + 2 * n * nb * 64
     assert p.workspace_bytes % 256 == 0
@@ -64,7 +64,7 @@ def test_nominal_geometry_picks_the_tile():
     from synth import CONFIGS
     from synth.geometry import projection_matrices
 
-    for name, pitch in (("tiny", 40), ("head256", 72)):
+    for name, pitch in (("tiny", 40), ("head256", 80)):
         cfg = CONFIGS[name]
         g = gmc.make_geometry(cfg.n_views, cfg.det_w, cfg.det_h, cfg.grid.shape, cfg.grid.voxel_mm, cfg.grid.origin_mm)
         assert gmc.Plan(g, projection_matrices(cfg.scan)).info()["tile_pitch"] == pitch
