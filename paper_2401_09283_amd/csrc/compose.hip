@@ -91,7 +91,8 @@ __global__ void k_setup(SetupArgs a) {
         const double vv = Ph[4] * x + Ph[5] * y + Ph[6] * z + Ph[7];
         const double w = Ph[8] * x + Ph[9] * y + Ph[10] * z + Ph[11];
         if (!(w > 0.0)) { bad = true; break; }
-        const double uh = u / w, vh = vv / w;
+        const double rw = 1.0 / w;   // tile bounds: one division per corner suffices
+        const double uh = u * rw, vh = vv * rw;
         umin = fmin(umin, uh); umax = fmax(umax, uh);
         vmin = fmin(vmin, vh); vmax = fmax(vmax, vh);
     }
@@ -160,8 +161,9 @@ __global__ void k_setup(SetupArgs a) {
                 const double y = o[1] + ((c & 2) ? ext[1] : 0.0);
                 const double w = Ph[8] * x + Ph[9] * y + Ph[10] * z + Ph[11];
                 if (!(w > 0.0)) { ok = false; break; }
-                const double uh = (Ph[0] * x + Ph[1] * y + Ph[2] * z + Ph[3]) / w;
-                const double vh = (Ph[4] * x + Ph[5] * y + Ph[6] * z + Ph[7]) / w;
+                const double rw = 1.0 / w;
+                const double uh = (Ph[0] * x + Ph[1] * y + Ph[2] * z + Ph[3]) * rw;
+                const double vh = (Ph[4] * x + Ph[5] * y + Ph[6] * z + Ph[7]) * rw;
                 ulo = fmin(ulo, uh); uhi = fmax(uhi, uh);
                 vlo = fmin(vlo, vh); vhi = fmax(vhi, vh);
             }

@@ -51,14 +51,20 @@ __device__ __forceinline__ float db3(float s) {
 }  // namespace
 
 // ------------------------------------------------------------------ sum of squared differences
+// Volume traversal without 64-bit division: blocks stride over (i, j) columns, threads
+// over k (z fastest, coalesced).
+#define FOR_EACH_VOXEL(nx, ny, nz)                                                             \
+    for (int col = blockIdx.x; col < (nx) * (ny); col += gridDim.x)                            \
+        for (int k = threadIdx.x; k < (nz); k += 256)
+
 __global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ I, float* __restrict__ grad,
                                                double* __restrict__ part, int nx, int ny, int nz) {
     __shared__ double sh[256];
-    const long long N = (long long)nx * ny * nz;
     const long long sx = (long long)ny * nz, sy = nz;
     double local = 0.0;
-    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < N; idx += (long long)gridDim.x * 256) {
-        const int k = (int)(idx % nz), j = (int)((idx / nz) % ny), i = (int)(idx / sx);
+    FOR_EACH_VOXEL(nx, ny, nz) {
+        const int i = col / ny, j = col % ny;
+        const long long idx = (long long)col * nz + k;
         const float c = I[idx];
         float g = 0.0f;
         float s = 0.0f;
@@ -127,14 +133,22 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a, double* __restrict__ h
     }
 }
 
-// hist [0..63] = h_b; then coef[64..127] = dH/dh_b; hist[128] = H
-__global__ void __launch_bounds__(64) k_hist_final(const double* __restrict__ hist_part, int nparts,
-                                                   double* __restrict__ hist) {
+// hist[b] = sum over blocks of the per-block partials (one block per bin, fixed-order tree)
+__global__ void __launch_bounds__(256) k_hist_reduce(const double* __restrict__ hist_part, int nparts,
+                                                     double* __restrict__ hist) {
+    __shared__ double sh[256];
+    const int b = blockIdx.x;
+    double v = 0.0;
+    for (int p = threadIdx.x; p < nparts; p += 256) v += hist_part[(long long)b * nparts + p];
+    const double s = block_sum(v, sh);
+    if (threadIdx.x == 0) hist[b] = s;
+}
+
+// coef[64..127] = dH/dh_b; hist[128] = H
+__global__ void __launch_bounds__(64) k_hist_final(double* __restrict__ hist) {
     __shared__ double sh[64];
     const int b = threadIdx.x;
-    double h = 0.0;
-    for (int p = 0; p < nparts; ++p) h += hist_part[(long long)b * nparts + p];
-    hist[b] = h;
+    const double h = hist[b];
     sh[b] = h;
     __syncthreads();
     double Z = 0.0;
@@ -176,10 +190,10 @@ __global__ void __launch_bounds__(256) k_entropy_tv_grad(GradArgs a) {
     if (threadIdx.x < HIST_BINS) coef[threadIdx.x] = (float)a.hist[HIST_BINS + threadIdx.x];
     __syncthreads();
     const long long sx = (long long)a.ny * a.nz, sy = a.nz;
-    const long long N = (long long)a.nx * sx;
     double tv = 0.0, gh2 = 0.0, gt2 = 0.0;
-    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < N; idx += (long long)gridDim.x * 256) {
-        const int k = (int)(idx % a.nz), j = (int)((idx / a.nz) % a.ny), i = (int)(idx / sx);
+    FOR_EACH_VOXEL(a.nx, a.ny, a.nz) {
+        const int i = col / a.ny, j = col % a.ny;
+        const long long idx = (long long)col * a.nz + k;
         // entropy seed
         const float s = (a.I[idx] - a.lo) * a.inv_d - 0.5f;
         const float fb = floorf(s);
@@ -238,7 +252,9 @@ hipError_t launch_loss_entropy_tv(const gmc_plan* p, const float* vol, double la
     k_hist<<<LOSS_BLOCKS, 256, 0, s>>>(ha, hist_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_hist_final<<<1, HIST_BINS, 0, s>>>(hist_part, LOSS_BLOCKS, hist_final);
+    k_hist_reduce<<<HIST_BINS, 256, 0, s>>>(hist_part, LOSS_BLOCKS, hist_final);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_hist_final<<<1, HIST_BINS, 0, s>>>(hist_final);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     GradArgs ga;
     ga.I = vol;

@@ -34,14 +34,22 @@ __global__ void k_bspline_theta(int n_views, int n_nodes, const double* __restri
     theta[q] = unit_of(k) * s;
 }
 
-__global__ void k_bspline_grad(int n_views, int n_nodes, const double* __restrict__ g, double* __restrict__ gc) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n_nodes * 6) return;
+// one block per coefficient (k, m): the threads split the views, then a fixed-order tree sum
+__global__ void __launch_bounds__(256) k_bspline_grad(int n_views, int n_nodes, const double* __restrict__ g,
+                                                      double* __restrict__ gc) {
+    __shared__ double sh[256];
+    const int q = blockIdx.x;
     const int k = q / n_nodes, m = q % n_nodes;
     const double h = (double)(n_views - 1) / (double)(n_nodes - 3);
     double s = 0.0;
-    for (int j = 0; j < n_views; ++j) s += g[6 * j + k] * bspline3(((double)j - (double)(m - 1) * h) / h);
-    gc[q] = unit_of(k) * s;
+    for (int j = threadIdx.x; j < n_views; j += 256) s += g[6 * j + k] * bspline3(((double)j - (double)(m - 1) * h) / h);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gc[q] = unit_of(k) * sh[0];
 }
 
 hipError_t launch_bspline_theta(int n_views, int n_nodes, const double* coeffs, double* theta, hipStream_t s) {
@@ -51,7 +59,7 @@ hipError_t launch_bspline_theta(int n_views, int n_nodes, const double* coeffs, 
 
 hipError_t launch_bspline_grad(int n_views, int n_nodes, const double* grad_theta, double* grad_coeffs,
                                hipStream_t s) {
-    k_bspline_grad<<<(n_nodes * 6 + 255) / 256, 256, 0, s>>>(n_views, n_nodes, grad_theta, grad_coeffs);
+    k_bspline_grad<<<n_nodes * 6, 256, 0, s>>>(n_views, n_nodes, grad_theta, grad_coeffs);
     return hipGetLastError();
 }
 
