@@ -123,7 +123,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="head256")
     ap.add_argument("--lr", type=float, default=0.05)
-    ap.add_argument("--cpu-views", type=int, default=16, help="views of the oracle's bounded CPU sample")
+    ap.add_argument("--cpu-views", type=int, default=160, help="views of the oracle's bounded CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one elementwise kernel over this many MiB first (HBM counter calibration)")

@@ -221,7 +221,7 @@ gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_p
     p->off_G = off; off = align256(off + n * 12 * sizeof(double));
     p->off_status = off; off = align256(off + sizeof(int));
     p->off_loss = off; off = align256(off + (4 * (size_t)LOSS_BLOCKS + 8) * sizeof(double));
-    p->off_hist = off; off = align256(off + ((size_t)HIST_BINS * LOSS_BLOCKS + 2 * HIST_BINS + 8) * sizeof(double));
+    p->off_hist = off; off = align256(off + ((size_t)HIST_BINS * HIST_BLOCKS + 2 * HIST_BINS + 8) * sizeof(double));
     p->ws_bytes = off;
     *out = p;
     return GMC_OK;

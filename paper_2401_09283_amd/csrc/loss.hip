@@ -246,13 +246,13 @@ hipError_t launch_loss_entropy_tv(const gmc_plan* p, const float* vol, double la
     const long long N = (long long)p->g.nx * p->g.ny * p->g.nz;
     const float inv_d = (float)((double)HIST_BINS / (hi - lo));
     HistArgs ha{vol, N, (float)lo, inv_d};
-    // hist scratch: [64][LOSS_BLOCKS] partials, then 129 finals
+    // hist scratch: [64][HIST_BLOCKS] partials, then 129 finals
     double* hist_part = hist;
-    double* hist_final = hist + (long long)HIST_BINS * LOSS_BLOCKS;
-    k_hist<<<LOSS_BLOCKS, 256, 0, s>>>(ha, hist_part);
+    double* hist_final = hist + (long long)HIST_BINS * HIST_BLOCKS;
+    k_hist<<<HIST_BLOCKS, 256, 0, s>>>(ha, hist_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_hist_reduce<<<HIST_BINS, 256, 0, s>>>(hist_part, LOSS_BLOCKS, hist_final);
+    k_hist_reduce<<<HIST_BINS, 256, 0, s>>>(hist_part, HIST_BLOCKS, hist_final);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_hist_final<<<1, HIST_BINS, 0, s>>>(hist_final);
     if ((e = hipGetLastError()) != hipSuccess) return e;
