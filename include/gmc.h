@@ -147,6 +147,18 @@ gmc_status gmc_bspline_theta(int32_t n_views, int32_t n_nodes, const double* coe
 /* Adjoint: grad_coeffs [6][n_nodes] = d/dcoeffs of <grad_theta, theta(coeffs)>. */
 gmc_status gmc_bspline_grad(int32_t n_views, int32_t n_nodes, const double* grad_theta, double* grad_coeffs,
                             void* hip_stream);
+/* The paper's motion model (Sec. II-B.1): an Akima spline per rigid parameter through
+ * n_nodes node values evenly spaced over the views (node m at view m (n_views - 1)/(n_nodes - 1),
+ * the first and the last node on the first and the last view). coeffs [6][n_nodes] float64
+ * node values in (mm, mm, mm, deg, deg, deg); theta [n_views][6] float64 in (mm, rad).
+ * 3 <= n_nodes <= 256, n_nodes <= n_views. */
+gmc_status gmc_akima_theta(int32_t n_views, int32_t n_nodes, const double* coeffs, double* theta,
+                           void* hip_stream);
+/* Adjoint at coeffs: grad_coeffs [6][n_nodes] = (d theta / d coeffs)^T grad_theta. The spline is
+ * not linear in its nodes (the node slopes weight neighbouring secants by their differences);
+ * |x|' is taken as sign(x), 0 at 0. */
+gmc_status gmc_akima_grad(int32_t n_views, int32_t n_nodes, const double* coeffs, const double* grad_theta,
+                          double* grad_coeffs, void* hip_stream);
 /* One Adam step (Kingma & Ba) on n float64 parameters x with gradient g and moments m, v;
  * step t >= 1. The paper's optimiser is gradient descent with decaying steps (Eq. 6). */
 gmc_status gmc_adam_step(int64_t n, double* x, const double* g, double* m, double* v, int32_t t, double lr,

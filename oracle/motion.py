@@ -10,6 +10,12 @@
   here is Adam (Kingma & Ba), which the paper's discussion suggests.
 * Reprojection error (Sec. IV): mean detector distance (mm) between points
   projected with the estimated and the true geometry.
+* The paper's own motion model (Sec. II-B.1) is an Akima spline per rigid parameter
+  with N_n nodes evenly spaced over the scan, the first on the first view and the last
+  on the last view. `akima_*` evaluate it from Akima's construction (secant slopes, two
+  extrapolated secants at each end, node slopes weighted by the differences of the
+  neighbouring secants, cubic Hermite pieces) and differentiate it in forward mode with
+  dual numbers (no hand-derived adjoint).
 """
 from __future__ import annotations
 
@@ -63,3 +69,113 @@ def adam_step(x, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mh = m / (1.0 - beta1 ** t)
     vh = v / (1.0 - beta2 ** t)
     return x - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ------------------------------------------------------------------------------ Akima spline
+
+class Dual:
+    """Value and gradient with respect to the node values (forward-mode differentiation)."""
+
+    def __init__(self, v, d):
+        self.v = float(v)
+        self.d = np.asarray(d, dtype=np.float64)
+
+    def _wrap(self, o):
+        return o if isinstance(o, Dual) else Dual(o, np.zeros_like(self.d))
+
+    def __add__(self, o):
+        o = self._wrap(o)
+        return Dual(self.v + o.v, self.d + o.d)
+
+    __radd__ = __add__
+
+    def __sub__(self, o):
+        o = self._wrap(o)
+        return Dual(self.v - o.v, self.d - o.d)
+
+    def __rsub__(self, o):
+        return self._wrap(o) - self
+
+    def __mul__(self, o):
+        o = self._wrap(o)
+        return Dual(self.v * o.v, self.v * o.d + o.v * self.d)
+
+    __rmul__ = __mul__
+
+    def __truediv__(self, o):
+        o = self._wrap(o)
+        return Dual(self.v / o.v, (self.d * o.v - self.v * o.d) / (o.v * o.v))
+
+
+def _dabs(x):
+    if not isinstance(x, Dual):
+        return abs(x)
+    s = 1.0 if x.v > 0 else (-1.0 if x.v < 0 else 0.0)
+    return Dual(abs(x.v), s * x.d)
+
+
+def _val(x):
+    return x.v if isinstance(x, Dual) else float(x)
+
+
+def akima_slopes(y, dx):
+    """Node slopes of Akima's interpolant of values y (list of Dual or float, n >= 3) at
+    uniformly spaced nodes (spacing dx)."""
+    n = len(y)
+    if n < 3:
+        raise ValueError("an Akima spline needs at least 3 nodes")
+    m = [(y[i + 1] - y[i]) / dx for i in range(n - 1)]
+    ext = [3.0 * m[0] - 2.0 * m[1], 2.0 * m[0] - m[1]] + m + [2.0 * m[-1] - m[-2], 3.0 * m[-1] - 2.0 * m[-2]]
+    t = []
+    for i in range(n):
+        a, b, c, d = ext[i], ext[i + 1], ext[i + 2], ext[i + 3]   # m_(i-2), m_(i-1), m_i, m_(i+1)
+        w1, w2 = _dabs(d - c), _dabs(b - a)
+        if _val(w1) + _val(w2) == 0.0:
+            t.append((b + c) * 0.5)
+        else:
+            t.append((w1 * b + w2 * c) / (w1 + w2))
+    return t
+
+
+def akima_eval(y, x_q, x_last):
+    """Akima interpolant of node values y on nodes evenly spaced over [0, x_last], at x_q."""
+    n = len(y)
+    dx = x_last / (n - 1)
+    t = akima_slopes(y, dx)
+    out = []
+    for xq in x_q:
+        i = min(int(math.floor(xq / dx)), n - 2)
+        s = (xq - i * dx) / dx
+        h00, h10 = 2 * s ** 3 - 3 * s ** 2 + 1, s ** 3 - 2 * s ** 2 + s
+        h01, h11 = -2 * s ** 3 + 3 * s ** 2, s ** 3 - s ** 2
+        out.append(y[i] * h00 + t[i] * (h10 * dx) + y[i + 1] * h01 + t[i + 1] * (h11 * dx))
+    return out
+
+
+def akima_theta(values, n_views):
+    """theta [n_views][6] (mm, rad) from Akima node values [6][n_nodes] (mm, deg); node m sits
+    at view m (n_views - 1)/(n_nodes - 1)."""
+    v = np.asarray(values, dtype=np.float64)
+    out = np.zeros((n_views, 6))
+    for k in range(6):
+        out[:, k] = [float(z) for z in akima_eval(list(v[k]), np.arange(n_views, dtype=np.float64), n_views - 1)]
+    return out * UNIT[None, :]
+
+
+def akima_jacobian(values_k, n_views):
+    """d theta_j / d node_m [n_views][n_nodes] for one rigid parameter (in node units)."""
+    y0 = np.asarray(values_k, dtype=np.float64)
+    n = len(y0)
+    y = [Dual(y0[i], np.eye(n)[i]) for i in range(n)]
+    ev = akima_eval(y, np.arange(n_views, dtype=np.float64), n_views - 1)
+    return np.array([e.d for e in ev])
+
+
+def akima_node_grad(values, grad_theta):
+    """dL/d nodes [6][n_nodes] from dL/dtheta [n_views][6] through theta = Akima(nodes) * unit."""
+    v = np.asarray(values, dtype=np.float64)
+    g = np.asarray(grad_theta, dtype=np.float64)
+    out = np.zeros_like(v)
+    for k in range(6):
+        out[k] = akima_jacobian(v[k], g.shape[0]).T @ (g[:, k] * UNIT[k])
+    return out

@@ -350,6 +350,24 @@ gmc_status gmc_bspline_grad(int32_t n_views, int32_t n_nodes, const double* grad
     return e == hipSuccess ? GMC_OK : hip_fail(e, "bspline adjoint");
 }
 
+gmc_status gmc_akima_theta(int32_t n_views, int32_t n_nodes, const double* coeffs, double* theta,
+                           void* hip_stream) {
+    if (n_views < 2 || n_nodes < 3 || n_nodes > 256 || n_nodes > n_views)
+        return fail(GMC_E_INVALID, "need n_views >= 2 and 3 <= n_nodes <= min(256, n_views)");
+    if (!coeffs || !theta) return fail(GMC_E_INVALID, "NULL argument");
+    hipError_t e = launch_akima_theta(n_views, n_nodes, coeffs, theta, (hipStream_t)hip_stream);
+    return e == hipSuccess ? GMC_OK : hip_fail(e, "akima");
+}
+
+gmc_status gmc_akima_grad(int32_t n_views, int32_t n_nodes, const double* coeffs, const double* grad_theta,
+                          double* grad_coeffs, void* hip_stream) {
+    if (n_views < 2 || n_nodes < 3 || n_nodes > 256 || n_nodes > n_views)
+        return fail(GMC_E_INVALID, "need n_views >= 2 and 3 <= n_nodes <= min(256, n_views)");
+    if (!coeffs || !grad_theta || !grad_coeffs) return fail(GMC_E_INVALID, "NULL argument");
+    hipError_t e = launch_akima_grad(n_views, n_nodes, coeffs, grad_theta, grad_coeffs, (hipStream_t)hip_stream);
+    return e == hipSuccess ? GMC_OK : hip_fail(e, "akima adjoint");
+}
+
 gmc_status gmc_adam_step(int64_t n, double* x, const double* g, double* m, double* v, int32_t t, double lr,
                          double beta1, double beta2, double eps, void* hip_stream) {
     if (n < 0 || t < 1) return fail(GMC_E_INVALID, "need n >= 0 and t >= 1");

@@ -111,6 +111,9 @@ hipError_t launch_loss_entropy_tv(const gmc_plan* p, const float* vol, double la
 hipError_t launch_bspline_theta(int n_views, int n_nodes, const double* coeffs, double* theta, hipStream_t s);
 hipError_t launch_bspline_grad(int n_views, int n_nodes, const double* grad_theta, double* grad_coeffs,
                                hipStream_t s);
+hipError_t launch_akima_theta(int n_views, int n_nodes, const double* coeffs, double* theta, hipStream_t s);
+hipError_t launch_akima_grad(int n_views, int n_nodes, const double* coeffs, const double* grad_theta,
+                             double* grad_coeffs, hipStream_t s);
 hipError_t launch_adam(long long n, double* x, const double* g, double* m, double* v, int t, double lr,
                        double b1, double b2, double eps, hipStream_t s);
 hipError_t launch_gd(long long n, double* x, const double* g, double step, hipStream_t s);

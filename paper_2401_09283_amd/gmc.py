@@ -186,6 +186,19 @@ def gmc_bspline_grad(n_views, n_nodes, grad_theta, grad_coeffs, stream=None):
           "gmc_bspline_grad")
 
 
+def gmc_akima_theta(n_views, n_nodes, coeffs, theta, stream=None):
+    check(lib().gmc_akima_theta(int(n_views), int(n_nodes), _ptr(coeffs, torch.float64, (6, n_nodes), "coeffs"),
+                                _ptr(theta, torch.float64, (n_views, 6), "theta"), _stream(stream)),
+          "gmc_akima_theta")
+
+
+def gmc_akima_grad(n_views, n_nodes, coeffs, grad_theta, grad_coeffs, stream=None):
+    check(lib().gmc_akima_grad(int(n_views), int(n_nodes), _ptr(coeffs, torch.float64, (6, n_nodes), "coeffs"),
+                               _ptr(grad_theta, torch.float64, (n_views, 6), "grad_theta"),
+                               _ptr(grad_coeffs, torch.float64, (6, n_nodes), "grad_coeffs"), _stream(stream)),
+          "gmc_akima_grad")
+
+
 def gmc_adam_step(x, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     n = x.numel()
     check(lib().gmc_adam_step(n, _ptr(x, torch.float64, x.shape, "x"), _ptr(g, torch.float64, x.shape, "g"),

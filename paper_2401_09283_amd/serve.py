@@ -332,6 +332,11 @@ def main(argv=None):
         out["sequential"]["rpe_final_mm_mean"] = float(np.mean([
             reprojection_error(inputs[r.rid]["P"], r.result["theta"], inputs[r.rid]["theta_true"],
                                _pitch(inputs[r.rid]["size"])) for r in seq]))
+        # offered load: arrival rate times the mean GPU time of one plain solve (> 1: the queue
+        # grows for as long as requests keep arriving, and latency is mostly waiting)
+        service = float(np.mean([r.t_done - r.t_admit for r in seq]))
+        out["sequential"]["mean_service_s"] = service
+        out["offered_load_rho"] = args.rate * service
         same = all(np.array_equal(a.result["coeffs"], b.result["coeffs"])
                    for a, b in zip(sorted(reqs, key=lambda r: r.rid), sorted(seq, key=lambda r: r.rid))
                    if a.status == "done")
