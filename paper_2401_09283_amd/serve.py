@@ -193,7 +193,7 @@ class GpuExecutor:
         fwd, vjp = [], []
         for r in reqs:
             s = r.state
-            gmc.gmc_bspline_theta(s.n_views, s.cfg.n_nodes, s.coeffs, s.theta)
+            s._theta()
             gmc.gmc_prepare(s.bp.plan, s.bp.P, s.theta, 1, s.bp.workspace)
             fwd.append(dict(plan=s.bp.plan, proj=s.proj, vol=s.vol, workspace=s.bp.workspace, phase=0,
                             flags=gmc.WORK_PREPARED))
@@ -207,7 +207,7 @@ class GpuExecutor:
         gmc.gmc_launch_batch(vjp)
         for r in reqs:
             s = r.state
-            gmc.gmc_bspline_grad(s.n_views, s.cfg.n_nodes, s.gtheta, s.gc)
+            s._coeff_grad()
             s.it += 1
             gmc.gmc_adam_step(s.coeffs, s.gc, s.m, s.v, s.it, s.cfg.lr, s.cfg.beta1, s.cfg.beta2, s.cfg.adam_eps)
         self.torch.cuda.synchronize()
@@ -216,7 +216,7 @@ class GpuExecutor:
         from . import gmc
 
         s = r.state
-        gmc.gmc_bspline_theta(s.n_views, s.cfg.n_nodes, s.coeffs, s.theta)
+        s._theta()
         return dict(coeffs=s.coeffs.cpu().numpy(), theta=s.theta.cpu().numpy())
 
     def release(self, r):

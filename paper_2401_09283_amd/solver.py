@@ -1,6 +1,6 @@
 """Gradient-based rigid motion estimation on one GPU (Sec. II-C, Fig. 2).
 
-One iteration: spline coefficients -> per-view rigid parameters (B-spline, Sec. II-B.1) ->
+One iteration: spline coefficients -> per-view rigid parameters (Akima or B-spline, Sec. II-B.1) ->
 composition and backprojection (Eq. 1, Eq. 3) -> volume loss and its seed -> VJP (Eq. 4-5)
 -> dL/dtheta (Eq. 2) -> dL/dcoefficients (spline adjoint) -> Adam step, or the paper's
 gradient descent with exponentially decaying steps (Eq. 6). Every step is a libgmc kernel
@@ -33,6 +33,7 @@ DEG = math.pi / 180.0
 class SolverConfig:
     n_iter: int = 100
     n_nodes: int = 20
+    motion: str = "bspline"       # "bspline" | "akima" (the paper's motion model, Sec. II-B.1)
     loss: str = "entropy_tv"      # "entropy_tv" | "sumsq"
     optimizer: str = "adam"       # "adam" | "gd"
     lr: float = 0.05              # Adam step (coefficient units: mm, deg)
@@ -41,6 +42,8 @@ class SolverConfig:
     adam_eps: float = 1e-8
     gd_s0: float = 100.0          # Eq. 6 initial step
     gd_decay: float = 0.97        # Eq. 6 decay factor
+    gd_first_step: float = 0.0    # > 0: s0 = gd_first_step / max|df/dx| at x = 0 (coefficient
+                                  # units), for losses whose scale differs from the paper's metric
     hist_lo: float = -0.01
     hist_hi: float = 0.06
     tv_eps: float = 1e-5
@@ -69,6 +72,23 @@ class MotionSolver:
         self.loss = torch.zeros(5, dtype=torch.float64, device=dev)
         self.lam = self.cfg.lam
         self.it = 0
+        self.gd_s0 = self.cfg.gd_s0
+        if self.cfg.motion not in ("bspline", "akima"):
+            raise ValueError("unknown motion model %r" % self.cfg.motion)
+
+    def _theta(self):
+        n, nn = self.n_views, self.cfg.n_nodes
+        if self.cfg.motion == "akima":
+            gmc.gmc_akima_theta(n, nn, self.coeffs, self.theta)
+        else:
+            gmc.gmc_bspline_theta(n, nn, self.coeffs, self.theta)
+
+    def _coeff_grad(self):
+        n, nn = self.n_views, self.cfg.n_nodes
+        if self.cfg.motion == "akima":
+            gmc.gmc_akima_grad(n, nn, self.coeffs, self.gtheta, self.gc)
+        else:
+            gmc.gmc_bspline_grad(n, nn, self.gtheta, self.gc)
 
     # ---------------------------------------------------------------- pieces of one iteration
     def _loss(self, lam):
@@ -87,12 +107,20 @@ class MotionSolver:
                 self.lam = 0.0
             return self.lam
         plan, ws = self.bp.plan, self.bp.workspace
-        gmc.gmc_bspline_theta(self.n_views, self.cfg.n_nodes, self.coeffs, self.theta)
-        gmc.gmc_prepare(plan, self.bp.P, self.theta, 0, ws)
+        self._theta()
+        gmc.gmc_prepare(plan, self.bp.P, self.theta, 1, ws)
         gmc.gmc_bp_forward(plan, self.proj, self.vol, ws)
         self._loss(0.0)
         l0 = self.loss.cpu().numpy()
         self.lam = float(math.sqrt(l0[3] / max(l0[4], 1e-300)))
+        if self.cfg.optimizer == "gd" and self.cfg.gd_first_step > 0.0:
+            # Eq. 6 with the initial step normalised by the first gradient
+            self._loss(self.lam)
+            gmc.gmc_bp_vjp(plan, self.proj, self.gvol, ws)
+            gmc.gmc_bp_vjp_finish(plan, self.gtheta, None, ws)
+            self._coeff_grad()
+            gmax = float(self.gc.abs().max())
+            self.gd_s0 = self.cfg.gd_first_step / max(gmax, 1e-300)
         return self.lam
 
     def iteration(self, events=None):
@@ -101,8 +129,7 @@ class MotionSolver:
         if self.lam is None:
             self.calibrate()
         c, plan, ws = self.cfg, self.bp.plan, self.bp.workspace
-        n, nn = self.n_views, c.n_nodes
-        gmc.gmc_bspline_theta(n, nn, self.coeffs, self.theta)
+        self._theta()
         gmc.gmc_prepare(plan, self.bp.P, self.theta, 1, ws)
         if events:
             events["f0"].record()
@@ -116,12 +143,12 @@ class MotionSolver:
         if events:
             events["v1"].record()
         gmc.gmc_bp_vjp_finish(plan, self.gtheta, None, ws)
-        gmc.gmc_bspline_grad(n, nn, self.gtheta, self.gc)
+        self._coeff_grad()
         self.it += 1
         if c.optimizer == "adam":
             gmc.gmc_adam_step(self.coeffs, self.gc, self.m, self.v, self.it, c.lr, c.beta1, c.beta2, c.adam_eps)
         elif c.optimizer == "gd":
-            gmc.gmc_gd_step(self.coeffs, self.gc, self.it - 1, c.gd_s0, c.gd_decay)
+            gmc.gmc_gd_step(self.coeffs, self.gc, self.it - 1, self.gd_s0, c.gd_decay)
         else:
             raise ValueError("unknown optimizer %r" % c.optimizer)
 
@@ -138,7 +165,7 @@ class MotionSolver:
                 hist[i].copy_(self.loss[0], non_blocking=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        gmc.gmc_bspline_theta(self.n_views, self.cfg.n_nodes, self.coeffs, self.theta)
+        self._theta()
         return dict(theta=self.theta.cpu().numpy(), coeffs=self.coeffs.cpu().numpy(),
                     losses=hist[:n_iter].cpu().tolist() if record_loss else [],
                     ms_per_iter=dt * 1e3 / max(n_iter, 1))
@@ -193,19 +220,30 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--lr", type=float, default=0.05)
     ap.add_argument("--loss", default="entropy_tv")
-    ap.add_argument("--optimizer", default="adam")
+    ap.add_argument("--optimizer", default=None, help="adam | gd (default: gd for Akima cases, else adam)")
+    ap.add_argument("--motion", default=None, help="bspline | akima (default: the case's motion model)")
+    ap.add_argument("--nodes", type=int, default=0, help="nodes of the estimated spline (default: the case's)")
+    ap.add_argument("--gd-s0", type=float, default=100.0)
+    ap.add_argument("--gd-decay", type=float, default=0.97)
+    ap.add_argument("--gd-first-step", type=float, default=None,
+                    help="normalise s0 so that the first step moves the largest coefficient this far")
     args = ap.parse_args(argv)
     cfg = CONFIGS[args.config]
+    motion = args.motion or cfg.motion_model
+    optimizer = args.optimizer or ("gd" if motion == "akima" else "adam")
+    first = args.gd_first_step if args.gd_first_step is not None else (0.5 if optimizer == "gd" else 0.0)
     case = make_case(args.config)
     bp = Backprojector.from_case(case)
     proj = torch.from_numpy(case.proj).to(bp.device)
-    solver = MotionSolver(bp, proj, SolverConfig(n_iter=args.iters, n_nodes=cfg.n_nodes, lr=args.lr, loss=args.loss,
-                                                 optimizer=args.optimizer))
+    solver = MotionSolver(bp, proj, SolverConfig(n_iter=args.iters, n_nodes=args.nodes or cfg.estimate_nodes, lr=args.lr,
+                                                 loss=args.loss, optimizer=optimizer, motion=motion, gd_s0=args.gd_s0,
+                                                 gd_decay=args.gd_decay, gd_first_step=first))
     rpe0 = reprojection_error(case.P, np.zeros_like(case.theta_true), case.theta_true, cfg.pitch_mm)
     out = solver.run(record_loss=True)
     rpe1 = reprojection_error(case.P, out["theta"], case.theta_true, cfg.pitch_mm)
     bp.check()
-    print(json.dumps(dict(config=args.config, iters=args.iters, loss=args.loss, optimizer=args.optimizer,
+    print(json.dumps(dict(config=args.config, iters=args.iters, loss=args.loss, optimizer=optimizer, motion=motion,
+                          nodes=solver.cfg.n_nodes, gd_s0=solver.gd_s0 if optimizer == "gd" else None,
                           lam=solver.lam, rpe_initial_mm=rpe0, rpe_final_mm=rpe1,
                           ms_per_iter=out["ms_per_iter"], loss_first=out["losses"][0], loss_last=out["losses"][-1])))
 

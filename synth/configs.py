@@ -13,6 +13,9 @@ head256   256^3 @ 1 mm, 496 views, 620x480 @ 0.616 mm; head phantom seed 10;
 head512   512^3 @ 0.5 mm, 496 views, 976x976 @ 0.308 mm; same seeds as head256.
 serve128  128^3 @ 2 mm, 248 views, 310x240 @ 1.232 mm (serving mix).
 serve384  384^3 @ 0.667 mm, 496 views, 620x480 @ 0.616 mm (serving mix).
+paper128  the paper's own simulation shapes (Sec. III-IV): 360 views over a full circle,
+          detector 500 rows x 700 columns @ 0.64 mm, estimation grid 128^3 @ 2 mm; head
+          phantom seed 20; motion seed 21: 10-node Akima spline, +-5 mm / +-5 deg.
 """
 from __future__ import annotations
 
@@ -22,7 +25,7 @@ import numpy as np
 
 from .filter import fdk_filter
 from .geometry import ScanGeometry, VolumeGrid, projection_matrices
-from .motion import random_motion
+from .motion import random_akima_motion, random_motion
 from .phantom import head_phantom, random_ellipsoids
 from .project import line_integrals
 
@@ -43,6 +46,12 @@ class CaseConfig:
     peak_mm: float
     peak_deg: float
     arc_deg: float = 200.0
+    motion_model: str = "bspline"   # "bspline" | "akima": spline of the simulated motion
+    est_nodes: int = 0              # nodes of the estimated spline (0: n_nodes)
+
+    @property
+    def estimate_nodes(self) -> int:
+        return self.est_nodes or self.n_nodes
 
     @property
     def scan(self) -> ScanGeometry:
@@ -65,6 +74,8 @@ CONFIGS = {
     "serve128": CaseConfig("serve128", 128, 2.0, 248, 310, 240, 1.232, "head", 1000, 2000, 20, 3.0, 2.0),
     "serve256": CaseConfig("serve256", 256, 1.0, 496, 620, 480, 0.616, "head", 1000, 2000, 20, 3.0, 2.0),
     "serve384": CaseConfig("serve384", 384, 2.0 / 3.0, 496, 620, 480, 0.616, "head", 1000, 2000, 20, 3.0, 2.0),
+    "paper128": CaseConfig("paper128", 128, 2.0, 360, 700, 500, 0.64, "head", 20, 21, 10, 5.0, 5.0,
+                           arc_deg=360.0, motion_model="akima", est_nodes=30),
 }
 
 
@@ -95,7 +106,9 @@ def make_case(name_or_cfg, with_motion: bool = True, phantom_seed: int | None = 
     scan = cfg.scan
     ph = make_phantom(cfg, phantom_seed)
     ms = cfg.motion_seed if motion_seed is None else motion_seed
-    if with_motion:
+    if with_motion and cfg.motion_model == "akima":
+        theta, coeff = random_akima_motion(ms, cfg.n_views, cfg.n_nodes, cfg.peak_mm, cfg.peak_deg)
+    elif with_motion:
         theta, coeff = random_motion(ms, cfg.n_views, cfg.n_nodes, cfg.peak_mm, cfg.peak_deg)
     else:
         theta, coeff = np.zeros((cfg.n_views, 6)), np.zeros((6, cfg.n_nodes))

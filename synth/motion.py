@@ -40,3 +40,26 @@ def random_motion(seed: int, n_views: int, n_nodes: int, peak_mm: float, peak_de
     scale = np.array([st, st, st, sr, sr, sr])
     c = c * scale[:, None]
     return B @ c.T, c
+
+
+def random_akima_motion(seed: int, n_views: int, n_nodes: int, peak_mm: float, peak_deg: float):
+    """(theta [n_views][6], node values [6][n_nodes] in (mm, deg)) of a random Akima-spline motion:
+    node values drawn per parameter, nodes evenly spaced from the first to the last view, each
+    spline zero-centred over the scan, translations and rotations scaled to their peaks. The
+    curves are evaluated with SciPy's Akima interpolator."""
+    from scipy.interpolate import Akima1DInterpolator
+
+    rng = np.random.default_rng(seed)
+    xn = np.linspace(0.0, n_views - 1.0, n_nodes)
+    xv = np.arange(n_views, dtype=np.float64)
+    y = rng.standard_normal((6, n_nodes))
+    th = np.stack([Akima1DInterpolator(xn, y[k])(xv) for k in range(6)], axis=1)
+    y = y - th.mean(axis=0)[:, None]   # a constant shift of the nodes shifts the curve
+    th = th - th.mean(axis=0)[None, :]
+    st = peak_mm / max(np.abs(th[:, :3]).max(), 1e-300)
+    sr = peak_deg / max(np.abs(th[:, 3:]).max(), 1e-300)
+    scale = np.array([st, st, st, sr, sr, sr])
+    y = y * scale[:, None]
+    th = th * scale[None, :]
+    th[:, 3:] = np.radians(th[:, 3:])
+    return th, y

@@ -247,6 +247,26 @@ def test_bspline_and_adam_match_oracle():
     assert np.allclose(xd.cpu().numpy(), xr, rtol=1e-13, atol=1e-13)
 
 
+@pytest.mark.parametrize("n_views,n_nodes", [(360, 10), (360, 30), (496, 3), (41, 41)])
+def test_akima_motion_model_matches_oracle(n_views, n_nodes):
+    """Sec. II-B.1 motion model: theta and its node-value adjoint against the FP64 oracle
+    (dual-number derivatives), including constant node rows (both slope weights vanish)."""
+    from oracle import motion
+
+    rng = np.random.default_rng(n_nodes)
+    c = rng.standard_normal((6, n_nodes)) * 3.0
+    c[5] = 0.75   # constant row
+    th = torch.empty((n_views, 6), dtype=torch.float64, device=DEV)
+    gmc.gmc_akima_theta(n_views, n_nodes, _t(c, torch.float64), th)
+    ref = motion.akima_theta(c, n_views)
+    assert np.max(np.abs(th.cpu().numpy() - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    g = rng.standard_normal((n_views, 6))
+    gc = torch.empty((6, n_nodes), dtype=torch.float64, device=DEV)
+    gmc.gmc_akima_grad(n_views, n_nodes, _t(c, torch.float64), _t(g, torch.float64), gc)
+    gref = motion.akima_node_grad(c, g)
+    assert np.max(np.abs(gc.cpu().numpy() - gref)) <= 1e-11 * max(1.0, np.max(np.abs(gref)))
+
+
 def test_autograd_function_matches_vjp(tiny):
     s = Setup(tiny.scan, tiny.grid, tiny.P, tiny.theta_true, tiny.proj)
     theta = s.theta_d.clone().requires_grad_(True)
