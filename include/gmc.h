@@ -138,6 +138,24 @@ gmc_status gmc_loss_sumsq_grad(const gmc_plan* plan, const float* vol, float* gr
 gmc_status gmc_loss_entropy_tv(const gmc_plan* plan, const float* vol, double lambda, double lo, double hi,
                                double eps, float* grad_vol, double* loss, void* workspace, void* hip_stream);
 
+/* Ray-driven forward projection under Phat_j = P_j T(theta_j) (Eq. 1): the adjoint partner of
+ * the backprojection, for simulating scans under motion and re-projecting volumes (Sec. III
+ * simulates its data by forward projection). proj_out[j][r][c] (float32 [n_views][det_h][det_w],
+ * overwritten) is the line integral, along the ray from the source -M^-1 p4 (Phat = [M | p4])
+ * through pixel (c, r), of the trilinear interpolant of vol (float32 [nx][ny][nz], values at the
+ * voxel centres, zero outside the grid), by the midpoint rule over equal steps of at most half
+ * the smallest voxel pitch (units: mm x volume units). Device pointers; the workspace's matrix
+ * area is overwritten. */
+gmc_status gmc_forward_project(const gmc_plan* plan, const float* vol, const double* P, const double* theta,
+                               float* proj_out, void* workspace, void* hip_stream);
+/* Several independently moving rigid parts: voxel p belongs to part labels[p] (uint8 [nx][ny][nz],
+ * values >= n_parts belong to no part); part k moves with theta[k] ([n_parts][n_views][6] float64)
+ * and proj_out is the sum of the parts' projections. 1 <= n_parts <= 255; labels may be NULL
+ * only for n_parts = 1. */
+gmc_status gmc_forward_project_parts(const gmc_plan* plan, const float* vol, const uint8_t* labels, int32_t n_parts,
+                                     const double* P, const double* theta, float* proj_out, void* workspace,
+                                     void* hip_stream);
+
 /* Motion model: uniform cubic B-spline per rigid parameter with n_nodes coefficients,
  * knots t_m = (m - 1) h, h = (n_views - 1)/(n_nodes - 3) (Sec. II-B.1 uses splines over
  * the views). coeffs [6][n_nodes] float64 in (mm, mm, mm, deg, deg, deg);

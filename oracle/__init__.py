@@ -81,6 +81,8 @@ def _L():
         _lib.oracle_chain.restype = None
         _lib.oracle_project_points.argtypes = [P, i64, P, P]
         _lib.oracle_project_points.restype = None
+        _lib.oracle_forward_project.argtypes = [P, P, P, i32, P, ctypes.c_double, i32, i32, P]
+        _lib.oracle_forward_project.restype = None
     return _lib
 
 
@@ -236,3 +238,18 @@ def voxel_centres(g: _Geom, idx) -> np.ndarray:
     i = idx // (g.nz * g.ny)
     return np.stack([g.origin[0] + i * g.voxel[0], g.origin[1] + j * g.voxel[1],
                      g.origin[2] + k * g.voxel[2]], axis=1)
+
+
+def forward_project(g: _Geom, vol, Phat, step_vox=0.5, labels=None, part=0, view_lo=0, view_hi=None):
+    """Ray-driven FP64 line integrals of the trilinear interpolant of vol (float32 [nx][ny][nz])
+    under each Phat: [view_hi - view_lo][det_h][det_w] float64 (midpoint rule, steps of at most
+    step_vox times the smallest voxel pitch). labels: optional uint8 volume; only voxels of
+    `part` count."""
+    v = _f32(vol)
+    Ph = _f64(Phat).reshape(-1, 12)
+    view_hi = g.n_views if view_hi is None else view_hi
+    out = np.zeros((g.n_views, g.det_h, g.det_w))
+    lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.uint8)
+    _L().oracle_forward_project(ctypes.byref(g), _ptr(v), None if lab is None else _ptr(lab), int(part), _ptr(Ph),
+                                float(step_vox), int(view_lo), int(view_hi), _ptr(out))
+    return out[view_lo:view_hi]

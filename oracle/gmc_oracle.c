@@ -373,3 +373,101 @@ void oracle_project_points(const double* Ph, int64_t n_pts, const double* pts, d
         out[3 * q + 2] = uvw[2];
     }
 }
+
+/* ---------------------------------------------------------------- ray-driven forward projection
+ *
+ * The adjoint partner of the backprojection (used to simulate scans under Phat_j): the line
+ * integral, along the ray from the source through pixel (c, r), of the trilinear interpolant
+ * of the volume (voxel values at the voxel centres, zero outside the grid).
+ *
+ * Ray: with Phat = [M | p4], the source is C = -M^-1 p4 and the points projecting to (c, r)
+ * are C + w M^-1 (c, r, 1)^T, w the depth. The interpolant is supported in the box of voxel
+ * coordinates [-1, n] per axis; the ray's w-interval inside that box is split into
+ * N = ceil(length / h) equal steps (h = step_vox times the smallest voxel pitch) and the
+ * integral is the midpoint sum over them (mm x volume units). Volume [i][j][k], k fastest;
+ * out [n_views][det_h][det_w]; labels (optional, 255 = none) select the voxels of part `part`. */
+static void mat3_inv(const double A[3][3], double B[3][3]) {
+    const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                       A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    B[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det;
+    B[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+    B[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+    B[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / det;
+    B[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+    B[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+    B[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det;
+    B[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+    B[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+}
+
+static double voxel_value(const og_geom* g, const float* vol, const uint8_t* labels, int part, long i, long j,
+                          long k) {
+    if (i < 0 || j < 0 || k < 0 || i >= g->nx || j >= g->ny || k >= g->nz) return 0.0;
+    const long idx = (i * g->ny + j) * g->nz + k;
+    if (labels && labels[idx] != part) return 0.0;
+    return (double)vol[idx];
+}
+
+static double trilinear(const og_geom* g, const float* vol, const uint8_t* labels, int part, const double q[3]) {
+    const double fi = floor(q[0]), fj = floor(q[1]), fk = floor(q[2]);
+    const double a = q[0] - fi, b = q[1] - fj, c = q[2] - fk;
+    const long i = (long)fi, j = (long)fj, k = (long)fk;
+    double s = 0.0;
+    for (int di = 0; di < 2; ++di)
+        for (int dj = 0; dj < 2; ++dj)
+            for (int dk = 0; dk < 2; ++dk) {
+                const double w = (di ? a : 1.0 - a) * (dj ? b : 1.0 - b) * (dk ? c : 1.0 - c);
+                s += w * voxel_value(g, vol, labels, part, i + di, j + dj, k + dk);
+            }
+    return s;
+}
+
+void oracle_forward_project(const og_geom* g, const float* vol, const uint8_t* labels, int32_t part,
+                            const double* Phat, double step_vox, int32_t view_lo, int32_t view_hi, double* out) {
+    const double vmin = fmin(g->voxel[0], fmin(g->voxel[1], g->voxel[2]));
+    const double h = step_vox * vmin;
+    const int n[3] = {g->nx, g->ny, g->nz};
+#pragma omp parallel for collapse(2) schedule(dynamic, 4)
+    for (int32_t jv = view_lo; jv < view_hi; ++jv)
+        for (int32_t r = 0; r < g->det_h; ++r) {
+            const double* Ph = Phat + 12 * jv;
+            const double M[3][3] = {{Ph[0], Ph[1], Ph[2]}, {Ph[4], Ph[5], Ph[6]}, {Ph[8], Ph[9], Ph[10]}};
+            double Mi[3][3];
+            mat3_inv(M, Mi);
+            double C[3];
+            for (int a = 0; a < 3; ++a) C[a] = -(Mi[a][0] * Ph[3] + Mi[a][1] * Ph[7] + Mi[a][2] * Ph[11]);
+            for (int32_t c = 0; c < g->det_w; ++c) {
+                double d[3];
+                for (int a = 0; a < 3; ++a) d[a] = Mi[a][0] * c + Mi[a][1] * r + Mi[a][2];
+                /* voxel coordinates: q(w) = (C + w d - origin) / voxel */
+                double q0[3], dq[3], t0 = -INFINITY, t1 = INFINITY;
+                int empty = 0;
+                for (int a = 0; a < 3; ++a) {
+                    q0[a] = (C[a] - g->origin[a]) / g->voxel[a];
+                    dq[a] = d[a] / g->voxel[a];
+                    const double lo = -1.0, hi = (double)n[a];
+                    if (dq[a] == 0.0) {
+                        if (q0[a] <= lo || q0[a] >= hi) empty = 1;
+                    } else {
+                        double ta = (lo - q0[a]) / dq[a], tb = (hi - q0[a]) / dq[a];
+                        if (ta > tb) { const double x = ta; ta = tb; tb = x; }
+                        t0 = fmax(t0, ta);
+                        t1 = fmin(t1, tb);
+                    }
+                }
+                double sum = 0.0;
+                if (!empty && t1 > t0) {
+                    const double len = (t1 - t0) * sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                    const long N = (long)ceil(len / h - 1e-9);   /* an exact multiple of h is not split further */
+                    const double dt = (t1 - t0) / (double)N;
+                    for (long s = 0; s < N; ++s) {
+                        const double t = t0 + ((double)s + 0.5) * dt;
+                        const double q[3] = {q0[0] + t * dq[0], q0[1] + t * dq[1], q0[2] + t * dq[2]};
+                        sum += trilinear(g, vol, labels, part, q);
+                    }
+                    sum *= len / (double)N;
+                }
+                out[((long)jv * g->det_h + r) * g->det_w + c] = sum;
+            }
+        }
+}

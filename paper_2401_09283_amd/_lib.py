@@ -23,7 +23,7 @@ WORK_PREPARED = 1
 EXPORTS = ["gmc_plan_create", "gmc_plan_destroy", "gmc_workspace_bytes", "gmc_plan_info", "gmc_compose",
            "gmc_backproject", "gmc_backproject_vjp", "gmc_prepare", "gmc_bp_forward", "gmc_bp_vjp",
            "gmc_bp_vjp_finish", "gmc_loss_sumsq_grad", "gmc_loss_entropy_tv",
-           "gmc_bspline_theta", "gmc_bspline_grad", "gmc_akima_theta", "gmc_akima_grad", "gmc_adam_step", "gmc_gd_step", "gmc_debug_project",
+           "gmc_bspline_theta", "gmc_bspline_grad", "gmc_akima_theta", "gmc_akima_grad", "gmc_forward_project", "gmc_forward_project_parts", "gmc_adam_step", "gmc_gd_step", "gmc_debug_project",
            "gmc_launch_batch", "gmc_check", "gmc_status_string", "gmc_last_error"]
 
 
@@ -76,6 +76,8 @@ def lib():
         "gmc_bspline_theta": ([i32, i32, vp, vp, vp], i32),
         "gmc_bspline_grad": ([i32, i32, vp, vp, vp], i32),
         "gmc_akima_theta": ([i32, i32, vp, vp, vp], i32),
+        "gmc_forward_project": ([vp, vp, vp, vp, vp, vp, vp], i32),
+        "gmc_forward_project_parts": ([vp, vp, vp, i32, vp, vp, vp, vp, vp], i32),
         "gmc_akima_grad": ([i32, i32, vp, vp, vp, vp], i32),
         "gmc_adam_step": ([i64, vp, vp, vp, vp, i32, f64, f64, f64, f64, vp], i32),
         "gmc_gd_step": ([i64, vp, vp, i32, f64, f64, vp], i32),

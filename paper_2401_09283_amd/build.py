@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgmc.so")
 
-SOURCES = ["api.hip", "compose.hip", "backproject.hip", "reduce.hip", "loss.hip", "motion.hip"]
+SOURCES = ["api.hip", "compose.hip", "backproject.hip", "reduce.hip", "loss.hip", "motion.hip", "project.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -311,6 +311,31 @@ gmc_status gmc_backproject_vjp(const gmc_plan* plan, const float* proj, const do
     return gmc_bp_vjp_finish(plan, grad_theta, grad_P, workspace, hip_stream);
 }
 
+gmc_status gmc_forward_project(const gmc_plan* plan, const float* vol, const double* P, const double* theta,
+                               float* proj_out, void* workspace, void* hip_stream) {
+    return gmc_forward_project_parts(plan, vol, nullptr, 1, P, theta, proj_out, workspace, hip_stream);
+}
+
+gmc_status gmc_forward_project_parts(const gmc_plan* plan, const float* vol, const uint8_t* labels, int32_t n_parts,
+                                     const double* P, const double* theta, float* proj_out, void* workspace,
+                                     void* hip_stream) {
+    gmc_status st = check_plan_ws(plan, workspace);
+    if (st != GMC_OK) return st;
+    if (!vol || !P || !theta || !proj_out) return fail(GMC_E_INVALID, "NULL array argument");
+    if (n_parts < 1 || n_parts > 255 || (n_parts > 1 && !labels))
+        return fail(GMC_E_INVALID, "need 1 <= n_parts <= 255 and labels when n_parts > 1");
+    const WS w = carve(plan, workspace);
+    const hipStream_t s = (hipStream_t)hip_stream;
+    const long long nv = plan->g.n_views;
+    for (int k = 0; k < n_parts; ++k) {
+        hipError_t e = launch_compose(theta + 6 * nv * k, P, w.Phat, nullptr, plan->g.n_views, s);
+        if (e != hipSuccess) return hip_fail(e, "compose");
+        e = launch_forward_project(plan, vol, labels, k, w.Phat, proj_out, k > 0, s);
+        if (e != hipSuccess) return hip_fail(e, "forward projection");
+    }
+    return GMC_OK;
+}
+
 gmc_status gmc_loss_sumsq_grad(const gmc_plan* plan, const float* vol, float* grad_vol, double* loss,
                                void* workspace, void* hip_stream) {
     gmc_status st = check_plan_ws(plan, workspace);

@@ -111,6 +111,8 @@ hipError_t launch_loss_entropy_tv(const gmc_plan* p, const float* vol, double la
 hipError_t launch_bspline_theta(int n_views, int n_nodes, const double* coeffs, double* theta, hipStream_t s);
 hipError_t launch_bspline_grad(int n_views, int n_nodes, const double* grad_theta, double* grad_coeffs,
                                hipStream_t s);
+hipError_t launch_forward_project(const gmc_plan* p, const float* vol, const uint8_t* labels, int part,
+                                  const double* Phat, float* out, int accumulate, hipStream_t s);
 hipError_t launch_akima_theta(int n_views, int n_nodes, const double* coeffs, double* theta, hipStream_t s);
 hipError_t launch_akima_grad(int n_views, int n_nodes, const double* coeffs, const double* grad_theta,
                              double* grad_coeffs, hipStream_t s);

@@ -186,6 +186,24 @@ def gmc_bspline_grad(n_views, n_nodes, grad_theta, grad_coeffs, stream=None):
           "gmc_bspline_grad")
 
 
+def gmc_forward_project(plan: Plan, vol, P, theta, proj_out, workspace, stream=None):
+    n = plan.geometry.n_views
+    check(lib().gmc_forward_project(plan.handle, _ptr(vol, torch.float32, plan.vol_shape, "vol"),
+                                    _ptr(P, torch.float64, (n, 3, 4), "P"), _ptr(theta, torch.float64, (n, 6), "theta"),
+                                    _ptr(proj_out, torch.float32, plan.proj_shape, "proj_out"), _ws(plan, workspace),
+                                    _stream(stream)), "gmc_forward_project")
+
+
+def gmc_forward_project_parts(plan: Plan, vol, labels, n_parts, P, theta, proj_out, workspace, stream=None):
+    n = plan.geometry.n_views
+    check(lib().gmc_forward_project_parts(plan.handle, _ptr(vol, torch.float32, plan.vol_shape, "vol"),
+                                          _ptr(labels, torch.uint8, plan.vol_shape, "labels", allow_none=n_parts == 1),
+                                          int(n_parts), _ptr(P, torch.float64, (n, 3, 4), "P"),
+                                          _ptr(theta, torch.float64, (n_parts, n, 6), "theta"),
+                                          _ptr(proj_out, torch.float32, plan.proj_shape, "proj_out"),
+                                          _ws(plan, workspace), _stream(stream)), "gmc_forward_project_parts")
+
+
 def gmc_akima_theta(n_views, n_nodes, coeffs, theta, stream=None):
     check(lib().gmc_akima_theta(int(n_views), int(n_nodes), _ptr(coeffs, torch.float64, (6, n_nodes), "coeffs"),
                                 _ptr(theta, torch.float64, (n_views, 6), "theta"), _stream(stream)),
