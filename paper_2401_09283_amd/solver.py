@@ -34,7 +34,8 @@ class SolverConfig:
     n_iter: int = 100
     n_nodes: int = 20
     motion: str = "bspline"       # "bspline" | "akima" (the paper's motion model, Sec. II-B.1)
-    loss: str = "entropy_tv"      # "entropy_tv" | "sumsq"
+    loss: str = "entropy_tv"      # "entropy_tv" | "sumsq" | "unet" (learned metric, timing only)
+    unet_channels: tuple = (8, 16, 32, 64)
     optimizer: str = "adam"       # "adam" | "gd"
     lr: float = 0.05              # Adam step (coefficient units: mm, deg)
     beta1: float = 0.9
@@ -73,6 +74,7 @@ class MotionSolver:
         self.lam = self.cfg.lam
         self.it = 0
         self.gd_s0 = self.cfg.gd_s0
+        self._unet = None
         if self.cfg.motion not in ("bspline", "akima"):
             raise ValueError("unknown motion model %r" % self.cfg.motion)
 
@@ -97,6 +99,12 @@ class MotionSolver:
             gmc.gmc_loss_entropy_tv(plan, self.vol, lam, c.hist_lo, c.hist_hi, c.tv_eps, self.gvol, self.loss, ws)
         elif c.loss == "sumsq":
             gmc.gmc_loss_sumsq_grad(plan, self.vol, self.gvol, self.loss[:1], ws)
+        elif c.loss == "unet":
+            if self._unet is None:
+                from .unet import UNetMetric
+
+                self._unet = UNetMetric(c.unet_channels, device=self.bp.device)
+            self.loss[0] = self._unet(self.vol, self.gvol)
         else:
             raise ValueError("unknown loss %r" % c.loss)
 
@@ -105,6 +113,8 @@ class MotionSolver:
         if self.cfg.loss != "entropy_tv" or self.lam is not None:
             if self.lam is None:
                 self.lam = 0.0
+            if self.cfg.loss != "entropy_tv" and self.cfg.optimizer == "gd" and self.cfg.gd_first_step > 0.0:
+                self._normalise_gd()
             return self.lam
         plan, ws = self.bp.plan, self.bp.workspace
         self._theta()
@@ -114,14 +124,21 @@ class MotionSolver:
         l0 = self.loss.cpu().numpy()
         self.lam = float(math.sqrt(l0[3] / max(l0[4], 1e-300)))
         if self.cfg.optimizer == "gd" and self.cfg.gd_first_step > 0.0:
-            # Eq. 6 with the initial step normalised by the first gradient
-            self._loss(self.lam)
-            gmc.gmc_bp_vjp(plan, self.proj, self.gvol, ws)
-            gmc.gmc_bp_vjp_finish(plan, self.gtheta, None, ws)
-            self._coeff_grad()
-            gmax = float(self.gc.abs().max())
-            self.gd_s0 = self.cfg.gd_first_step / max(gmax, 1e-300)
+            self._normalise_gd()
         return self.lam
+
+    def _normalise_gd(self):
+        """Eq. 6 with the initial step normalised by the gradient at the current estimate."""
+        plan, ws = self.bp.plan, self.bp.workspace
+        self._theta()
+        gmc.gmc_prepare(plan, self.bp.P, self.theta, 1, ws)
+        gmc.gmc_bp_forward(plan, self.proj, self.vol, ws)
+        self._loss(self.lam if self.lam is not None else 0.0)
+        gmc.gmc_bp_vjp(plan, self.proj, self.gvol, ws)
+        gmc.gmc_bp_vjp_finish(plan, self.gtheta, None, ws)
+        self._coeff_grad()
+        gmax = float(self.gc.abs().max())
+        self.gd_s0 = self.cfg.gd_first_step / max(gmax, 1e-300)
 
     def iteration(self, events=None):
         """Launch one iteration on the current stream. events: optional dict of
@@ -227,6 +244,7 @@ def main(argv=None):
     ap.add_argument("--gd-decay", type=float, default=0.97)
     ap.add_argument("--gd-first-step", type=float, default=None,
                     help="normalise s0 so that the first step moves the largest coefficient this far")
+    ap.add_argument("--unet-channels", default="8,16,32,64", help="feature maps per level of the U-Net metric")
     args = ap.parse_args(argv)
     cfg = CONFIGS[args.config]
     motion = args.motion or cfg.motion_model
@@ -237,7 +255,8 @@ def main(argv=None):
     proj = torch.from_numpy(case.proj).to(bp.device)
     solver = MotionSolver(bp, proj, SolverConfig(n_iter=args.iters, n_nodes=args.nodes or cfg.estimate_nodes, lr=args.lr,
                                                  loss=args.loss, optimizer=optimizer, motion=motion, gd_s0=args.gd_s0,
-                                                 gd_decay=args.gd_decay, gd_first_step=first))
+                                                 gd_decay=args.gd_decay, gd_first_step=first,
+                                                 unet_channels=tuple(int(x) for x in args.unet_channels.split(","))))
     rpe0 = reprojection_error(case.P, np.zeros_like(case.theta_true), case.theta_true, cfg.pitch_mm)
     out = solver.run(record_loss=True)
     rpe1 = reprojection_error(case.P, out["theta"], case.theta_true, cfg.pitch_mm)
