@@ -86,8 +86,11 @@ gmc_status gmc_plan_destroy(gmc_plan* plan);
 /* Bytes of device workspace every call on this plan needs (256-byte aligned pointer). */
 size_t gmc_workspace_bytes(const gmc_plan* plan);
 /* Launch configuration chosen by the plan: out[0] brick x, out[1] brick y, out[2] brick z,
- * out[3] tile pitch (floats), out[4] tile rows, out[5] number of bricks. HOST pointer. */
-gmc_status gmc_plan_info(const gmc_plan* plan, int64_t out[6]);
+ * out[3] tile pitch (floats), out[4] tile rows, out[5] number of bricks, out[6] and out[7]
+ * view chunks per brick of the forward and of the VJP (each brick's views are split over
+ * that many workgroups; the forward then adds the chunks' partial volumes in chunk order,
+ * so results do not depend on scheduling). HOST pointer. */
+gmc_status gmc_plan_info(const gmc_plan* plan, int64_t out[8]);
 
 /* Eq. 1 and the derivative matrices of Eq. 2, FP64.
  * theta [n_views][6] (tx,ty,tz mm; rx,ry,rz rad), P [n_views][3][4] ->

@@ -119,6 +119,7 @@ struct WS {
     int* status;
     double* loss;
     double* hist;
+    float* vpart;
 };
 
 WS carve(const gmc_plan* p, void* ws) {
@@ -132,6 +133,7 @@ WS carve(const gmc_plan* p, void* ws) {
     w.status = (int*)(b + p->off_status);
     w.loss = (double*)(b + p->off_loss);
     w.hist = (double*)(b + p->off_hist);
+    w.vpart = (float*)(b + p->off_vpart);
     return w;
 }
 
@@ -142,7 +144,7 @@ gmc_status check_plan_ws(const gmc_plan* p, const void* ws) {
     return GMC_OK;
 }
 
-BpArgs bp_args(const gmc_plan* p, const float* proj, const WS& w) {
+BpArgs bp_args(const gmc_plan* p, const float* proj, const WS& w, bool vjp) {
     BpArgs a;
     a.proj = proj;
     a.desc = w.desc;
@@ -159,7 +161,9 @@ BpArgs bp_args(const gmc_plan* p, const float* proj, const WS& w) {
     a.nby = p->nby;
     a.nbz = p->nbz;
     a.n_bricks = p->n_bricks;
-    a.per_xcd = (p->n_bricks + 7) / 8;
+    a.vsplit = vjp ? p->vsplit_vjp : p->vsplit_fwd;
+    a.vpart = w.vpart;
+    a.per_xcd = (int)(((long long)p->n_bricks * a.vsplit + 7) / 8);
     a.dx = (float)p->g.voxel_mm[0];
     a.dy = (float)p->g.voxel_mm[1];
     a.dz = (float)p->g.voxel_mm[2];
@@ -212,6 +216,20 @@ gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_p
             }
         p->tile_cfg = choose_tile_cfg(p, P_nominal);
     }
+    // Each brick's views are split into chunks, one workgroup per (brick, chunk). The items of
+    // a launch are numbered chunk-major and handed to the eight XCDs in contiguous ranges, so
+    // with 8 chunks every XCD gets one chunk of the whole volume (bricks near the ends of the
+    // cone are cheaper: whole-volume ranges keep the XCDs equally loaded), and shorter items
+    // leave a shorter tail at the end of the launch. The VJP's partials are per view already;
+    // the forward pays one partial volume per extra chunk (capped at 4 GiB) and a summation,
+    // so it uses 4 chunks once the volume alone fills the GPU's 1536 workgroup slots twice.
+    {
+        const long long nv = g->n_views;
+        const long long vol_bytes = (long long)g->nx * g->ny * g->nz * (long long)sizeof(float);
+        const long long fwd = std::min<long long>({nb < 3072 ? 8LL : 4LL, nv, 1 + (4LL << 30) / vol_bytes});
+        p->vsplit_fwd = (int)std::max<long long>(1, fwd);
+        p->vsplit_vjp = (int)std::min<long long>(nb < 3072 ? 16LL : 8LL, nv);
+    }
     const size_t n = (size_t)g->n_views;
     size_t off = 0;
     p->off_phat = off; off = align256(off + n * 12 * sizeof(double));
@@ -222,6 +240,8 @@ gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_p
     p->off_status = off; off = align256(off + sizeof(int));
     p->off_loss = off; off = align256(off + (4 * (size_t)LOSS_BLOCKS + 8) * sizeof(double));
     p->off_hist = off; off = align256(off + ((size_t)HIST_BINS * HIST_BLOCKS + 2 * HIST_BINS + 8) * sizeof(double));
+    p->off_vpart = off;
+    off = align256(off + (size_t)(p->vsplit_fwd - 1) * (size_t)g->nx * g->ny * g->nz * sizeof(float));
     p->ws_bytes = off;
     *out = p;
     return GMC_OK;
@@ -234,7 +254,7 @@ gmc_status gmc_plan_destroy(gmc_plan* plan) {
 
 size_t gmc_workspace_bytes(const gmc_plan* plan) { return plan ? plan->ws_bytes : 0; }
 
-gmc_status gmc_plan_info(const gmc_plan* plan, int64_t out[6]) {
+gmc_status gmc_plan_info(const gmc_plan* plan, int64_t out[8]) {
     if (!plan || !out) return fail(GMC_E_INVALID, "NULL argument");
     out[0] = BXY;
     out[1] = BXY;
@@ -242,6 +262,8 @@ gmc_status gmc_plan_info(const gmc_plan* plan, int64_t out[6]) {
     out[3] = TILE_CFGS[plan->tile_cfg].tp;
     out[4] = TILE_CFGS[plan->tile_cfg].th;
     out[5] = plan->n_bricks;
+    out[6] = plan->vsplit_fwd;
+    out[7] = plan->vsplit_vjp;
     return GMC_OK;
 }
 
@@ -264,9 +286,10 @@ gmc_status gmc_bp_forward(const gmc_plan* plan, const float* proj, float* vol, v
     gmc_status st = check_plan_ws(plan, workspace);
     if (st != GMC_OK) return st;
     if (!proj || !vol) return fail(GMC_E_INVALID, "NULL array argument");
-    BpArgs a = bp_args(plan, proj, carve(plan, workspace));
+    BpArgs a = bp_args(plan, proj, carve(plan, workspace), false);
     a.vol = vol;
     hipError_t e = launch_bp(plan, a, false, (hipStream_t)hip_stream);
+    if (e == hipSuccess && a.vsplit > 1) e = launch_sum_chunks(a, (hipStream_t)hip_stream);
     return e == hipSuccess ? GMC_OK : hip_fail(e, "backprojection");
 }
 
@@ -275,7 +298,7 @@ gmc_status gmc_bp_vjp(const gmc_plan* plan, const float* proj, const float* grad
     gmc_status st = check_plan_ws(plan, workspace);
     if (st != GMC_OK) return st;
     if (!proj || !grad_vol) return fail(GMC_E_INVALID, "NULL array argument");
-    BpArgs a = bp_args(plan, proj, carve(plan, workspace));
+    BpArgs a = bp_args(plan, proj, carve(plan, workspace), true);
     a.gvol = grad_vol;
     hipError_t e = launch_bp(plan, a, true, (hipStream_t)hip_stream);
     return e == hipSuccess ? GMC_OK : hip_fail(e, "vjp");
@@ -461,18 +484,20 @@ gmc_status gmc_launch_batch(const gmc_work* items, int32_t n_items, void* hip_st
             if (done[q] || it.phase != lead.phase || it.plan->g.weighting != lead.plan->g.weighting ||
                 it.plan->g.grad_mode != lead.plan->g.grad_mode)
                 continue;
-            BpArgs ba = bp_args(it.plan, it.proj, carve(it.plan, it.workspace));
+            BpArgs ba = bp_args(it.plan, it.proj, carve(it.plan, it.workspace), it.phase == 1);
             ba.vol = it.vol;
             ba.gvol = it.grad_vol;
             tab.item[tab.n] = ba;
             tab.begin[tab.n] = tab.total;
-            tab.total += it.plan->n_bricks;
+            tab.total += it.plan->n_bricks * ba.vsplit;
             tab.n++;
             cfg = std::max(cfg, it.plan->tile_cfg);
             done[q] = true;
         }
         tab.per_xcd = (tab.total + 7) / 8;
         hipError_t e = launch_bp_batch(cfg, lead.plan->g.weighting, lead.plan->g.grad_mode, tab, lead.phase == 1, s);
+        for (int e2 = 0; e2 < tab.n && e == hipSuccess && lead.phase == 0; ++e2)
+            e = launch_sum_chunks(tab.item[e2], s);
         if (e != hipSuccess) return hip_fail(e, "batched backprojection");
     }
     for (int32_t q = 0; q < n_items; ++q) {

@@ -310,16 +310,22 @@ __device__ __forceinline__ BrickDesc load_desc(const __attribute__((address_spac
     return d;
 }
 
-// The work of one brick over all views; shared by the single-plan kernel and the batched one.
+// The work of one item (a brick and a contiguous chunk of its views); shared by the
+// single-plan kernel and the batched one. Item q is brick q % n_bricks and chunk q / n_bricks;
+// chunk c covers views [c n / vsplit, (c + 1) n / vsplit). The forward of chunk 0 writes the
+// volume, chunk c > 0 its own partial volume (summed afterwards in a fixed order); the VJP
+// partials are per view and brick, so every chunk writes its own views' rows.
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
 __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __restrict__ desc,
                                          const float* __restrict__ proj, float* __restrict__ vol,
-                                         const float* __restrict__ gvol, float* __restrict__ part, const int brick,
+                                         const float* __restrict__ gvol, float* __restrict__ part, const int item,
                                          float* __restrict__ sT, float2* __restrict__ sCol, float2* __restrict__ sRow,
                                          float* __restrict__ sRed) {
     constexpr int PLANE = TP * TH;
     constexpr int NSEG = (TP + 63) / 64;
     static_assert(BZ % 8 == 0, "the forward samples a column in groups of 8");
+    const int brick = item % a.n_bricks, chunk = item / a.n_bricks;
+    const int v_lo = chunk * a.n_views / a.vsplit, v_hi = (chunk + 1) * a.n_views / a.vsplit;
     const int bj = brick % a.nby;
     const int bi = (brick / a.nby) % a.nbx;
     const int bk = brick / (a.nby * a.nbx);
@@ -414,14 +420,17 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
         }
     };
 
-    BrickDesc cur = load_desc(descs);
-    stage(cur, 0, 0);
+    BrickDesc cur;
+    if (v_lo < v_hi) {
+        cur = load_desc(descs + (long long)v_lo * dstride);
+        stage(cur, v_lo, v_lo & 1);
+    }
     int prev_ou = 0, prev_ov = 0;
-    for (int v = 0; v < a.n_views; ++v) {
+    for (int v = v_lo; v < v_hi; ++v) {
         const int buf = v & 1;
         __builtin_amdgcn_s_waitcnt(0);   // this wave's tile loads of view v have landed in LDS
         __syncthreads();                 // ... and everybody's; buffer buf^1 is free again
-        if (VJP && v > 0 && t < 14) {
+        if (VJP && v > v_lo && t < 14) {
             float s;
             if (t < 12) {
                 const float* rb = sRed + ((v - 1) & 1) * 48;
@@ -432,7 +441,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
             part[((long long)(v - 1) * a.n_bricks + brick) * PART_STRIDE + t] = s;
         }
         BrickDesc nxt;
-        if (v + 1 < a.n_views) {
+        if (v + 1 < v_hi) {
             nxt = load_desc(descs + (long long)(v + 1) * dstride);
             stage(nxt, v + 1, buf ^ 1);
         }
@@ -604,13 +613,13 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                 rb[2] = red[2];
             }
         }
-        if (v + 1 < a.n_views) cur = nxt;
+        if (v + 1 < v_hi) cur = nxt;
     }
 
     if (VJP) {
         __syncthreads();
-        const int v = a.n_views;
-        if (v > 0 && t < 14) {
+        const int v = v_hi;
+        if (v > v_lo && t < 14) {
             float s;
             if (t < 12) {
                 const float* rb = sRed + ((v - 1) & 1) * 48;
@@ -621,7 +630,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
             part[((long long)(v - 1) * a.n_bricks + brick) * PART_STRIDE + t] = s;
         }
     } else if (col_in) {
-        float* out = vol + col_off;
+        float* out = (chunk == 0 ? vol : a.vpart + (long long)(chunk - 1) * a.nx * a.ny * a.nz) + col_off;
 #pragma unroll
         for (int k = 0; k < BZ; ++k)
             if (k0 + k < a.nz) out[k] = acc[k];
@@ -645,13 +654,13 @@ __global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH))
          const float* __restrict__ gvol, float* __restrict__ part) {
     __shared__ BpShared<TP, TH> sh;
     const int blk = blockIdx.x;
-    const int brick = (blk & 7) * a.per_xcd + (blk >> 3);
-    if (brick >= a.n_bricks) return;
-    bp_brick<TP, TH, BZ, WEIGHT, GRAD, VJP>(a, desc, proj, vol, gvol, part, brick, sh.sT, sh.sCol, sh.sRow, sh.sRed);
+    const int item = (blk & 7) * a.per_xcd + (blk >> 3);
+    if (item >= a.n_bricks * a.vsplit) return;
+    bp_brick<TP, TH, BZ, WEIGHT, GRAD, VJP>(a, desc, proj, vol, gvol, part, item, sh.sT, sh.sCol, sh.sRow, sh.sRed);
 }
 
-// Several plans in one launch: the bricks of all items form one index space (item q owns
-// [begin_q, begin_q + n_bricks_q)), mapped to XCDs like a single plan's bricks.
+// Several plans in one launch: the work items of all plans form one index space (plan q owns
+// [begin_q, begin_q + n_bricks_q vsplit_q)), mapped to XCDs like a single plan's items.
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
 __global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH)) k_bp_batch(BatchTable tab) {
     __shared__ BpShared<TP, TH> sh;
@@ -721,6 +730,24 @@ hipError_t launch_bp_batch(int tile_cfg, int weighting, int grad_mode, const Bat
         case 2: return launch_batch_cfg<TILE_CFGS[2].tp, TILE_CFGS[2].th, BRICK_Z>(weighting, grad_mode, tab, vjp, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+// vol += partial volumes of chunks 1 .. vsplit-1, added in chunk order (deterministic)
+__global__ void k_sum_chunks(float* __restrict__ vol, const float* __restrict__ vpart, long long n, int n_parts) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        float x = vol[e];
+        for (int c = 0; c < n_parts; ++c) x += vpart[c * n + e];
+        vol[e] = x;
+    }
+}
+
+hipError_t launch_sum_chunks(const BpArgs& a, hipStream_t s) {
+    if (a.vsplit <= 1) return hipSuccess;
+    const long long n = (long long)a.nx * a.ny * a.nz;
+    const unsigned grid = (unsigned)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(grid), dim3(256), 0, s, a.vol, (const float*)a.vpart, n, a.vsplit - 1);
+    return hipGetLastError();
 }
 
 hipError_t launch_bp(const gmc_plan* p, const BpArgs& a, bool vjp, hipStream_t s) {

@@ -66,8 +66,9 @@ struct gmc_plan {
     int bz;                      // brick depth (voxels along z)
     int nbx, nby, nbz, n_bricks;
     int tile_cfg;                // index into TILE_CFGS
+    int vsplit_fwd, vsplit_vjp;  // view chunks per brick (items = bricks x chunks) of each pass
     // workspace layout (byte offsets)
-    size_t off_phat, off_dphat, off_desc, off_part, off_G, off_status, off_loss, off_hist, ws_bytes;
+    size_t off_phat, off_dphat, off_desc, off_part, off_G, off_status, off_loss, off_hist, off_vpart, ws_bytes;
 };
 
 namespace gmc {
@@ -81,9 +82,11 @@ struct BpArgs {
     int nx, ny, nz, W, H, n_views, nbx, nby, nbz, n_bricks, per_xcd;
     float dx, dy, dz;
     long long plane;     // W*H
+    int vsplit;          // view chunks per brick: work item q is brick q % n_bricks, chunk q / n_bricks
+    float* vpart;        // forward partial volumes of chunks 1 .. vsplit-1 ([vsplit-1][nx*ny*nz])
 };
 
-// Several plans in one launch (serving): bricks of item q are [begin[q], begin[q] + n_bricks).
+// Several plans in one launch (serving): work items of plan q are [begin[q], begin[q] + n_bricks * vsplit).
 constexpr int MAX_BATCH = 16;
 struct BatchTable {
     BpArgs item[MAX_BATCH];
@@ -99,6 +102,8 @@ hipError_t launch_bp(const gmc_plan* p, const BpArgs& a, bool vjp, hipStream_t s
 // one launch over all items of tab; every plan must share weighting and gradient mode, and
 // tile_cfg must be at least each plan's own tile configuration
 hipError_t launch_bp_batch(int tile_cfg, int weighting, int grad_mode, const BatchTable& tab, bool vjp, hipStream_t s);
+// vol += sum of the chunk partial volumes (fixed order), for a forward run with a.vsplit > 1
+hipError_t launch_sum_chunks(const BpArgs& a, hipStream_t s);
 hipError_t launch_reduce_chain(const gmc_plan* p, const float* part, const double* dPhat, double* G,
                                double* grad_theta, double* grad_P, hipStream_t s);
 hipError_t launch_debug_project(const gmc_plan* p, const BrickDesc* desc, long long n, const int64_t* voxel,

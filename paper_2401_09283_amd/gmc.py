@@ -69,9 +69,10 @@ class Plan:
         return int(lib().gmc_workspace_bytes(self.handle))
 
     def info(self) -> dict:
-        out = (ctypes.c_int64 * 6)()
+        out = (ctypes.c_int64 * 8)()
         check(lib().gmc_plan_info(self.handle, out), "gmc_plan_info")
-        return dict(brick=(out[0], out[1], out[2]), tile_pitch=out[3], tile_rows=out[4], n_bricks=out[5])
+        return dict(brick=(out[0], out[1], out[2]), tile_pitch=out[3], tile_rows=out[4], n_bricks=out[5],
+                    view_chunks=(out[6], out[7]))
 
     @property
     def vol_shape(self):

@@ -60,6 +60,24 @@ def test_plan_bricks_and_workspace():
     assert p.workspace_bytes % 256 == 0
 
 
+def test_view_chunks_follow_the_brick_count():
+    # 12 bricks and 10 views: the views of every brick split into as many chunks as there are
+    # views (forward 8, VJP 10), with room for the forward's seven extra partial volumes
+    p = gmc.Plan(_geom())
+    assert p.info()["view_chunks"] == (8, 10)
+    assert p.workspace_bytes >= 7 * 20 * 18 * 17 * 4
+    # never more chunks than views
+    assert gmc.Plan(_geom(n_views=2)).info()["view_chunks"] == (2, 2)
+    assert gmc.Plan(_geom(n_views=1)).info()["view_chunks"] == (1, 1)
+    # a volume that fills the GPU by its bricks alone: 4 forward chunks, 8 VJP chunks
+    g = gmc.make_geometry(16, 64, 64, (256, 256, 256), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+    info = gmc.Plan(g).info()
+    assert info["n_bricks"] == 16 * 16 * 32 and info["view_chunks"] == (4, 8)
+    # the forward's partial volumes stay within 4 GiB
+    g = gmc.make_geometry(16, 64, 64, (1024, 1024, 1024), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+    assert gmc.Plan(g).info()["view_chunks"] == (2, 8)
+
+
 def test_nominal_geometry_picks_the_tile():
     from synth import CONFIGS
     from synth.geometry import projection_matrices
