@@ -11,9 +11,17 @@ each request's arithmetic is the same as when it runs alone, so its result is bi
 identical. A request that finishes its iterations retires and frees its memory; the next
 tick admits new arrivals.
 
+Which active requests a tick advances is the policy: ``"all"`` advances every active request
+(processor sharing), ``"srpt"`` (the default) advances the requests with the least remaining work first
+(remaining iterations times the voxel-view updates of one iteration), adding requests to the
+tick until its work reaches ``tick_work`` updates (at least one request): small requests
+share launches and finish early, a large request runs alone once nothing smaller waits.
+Results do not depend on the policy: every request's own iterations are the same.
+
 The scheduler is independent of the GPU: ``Server`` drives an executor with four calls
-(footprint, admit, step, release), so its admission and retirement logic is tested on the
-CPU with a fake executor and a fake clock.
+(footprint, admit, step, release) and an optional fifth (work: updates per iteration), so its
+admission, policy and retirement logic is tested on the CPU with a fake executor and a fake
+clock.
 
 ``python -m paper_2401_09283_amd.serve`` runs the synthetic serving workload (Poisson
 arrivals at 2 requests/s drawn from 128^3 x 248, 256^3 x 496 and 384^3 x 496 views, 30
@@ -54,10 +62,15 @@ class Request:
 class Server:
     """Continuous batching over an executor (see module docstring)."""
 
-    def __init__(self, executor, hbm_budget_bytes: int, max_active: int = 16, clock=None, sleep=None):
+    def __init__(self, executor, hbm_budget_bytes: int, max_active: int = 16, clock=None, sleep=None,
+                 policy: str = "srpt", tick_work: float = 8e9):
+        if policy not in ("all", "srpt"):
+            raise ValueError("policy must be 'all' or 'srpt'")
         self.ex = executor
         self.budget = int(hbm_budget_bytes)
         self.max_active = int(max_active)
+        self.policy = policy
+        self.tick_work = float(tick_work)
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
         self.used = 0
@@ -98,29 +111,45 @@ class Server:
                 if pending:
                     self.sleep(max(0.0, pending[0].arrival - now()))
                 continue
+            batch = self._pick(active)
             try:
-                self.ex.step(active)
+                self.ex.step(batch)
             except Exception as e:
                 # a failed tick fails its requests and frees their slots; others go on
-                for r in active:
+                for r in batch:
                     r.status, r.error, r.t_done = "failed", "step: %s" % e, now()
                     self._release(r)
-                active = []
+                active = [r for r in active if r.status == "active"]
                 continue
             self.ticks += 1
-            self.batch_sizes.append(len(active))
+            self.batch_sizes.append(len(batch))
             t = now()
-            still = []
-            for r in active:
+            for r in batch:
                 r.iters_done += 1
                 if r.iters_done >= r.n_iter:
                     r.result = self.ex.result(r)
                     r.status, r.t_done = "done", t
                     self._release(r)
-                else:
-                    still.append(r)
-            active = still
+            active = [r for r in active if r.status == "active"]
         return reqs
+
+    def _work(self, r):
+        f = getattr(self.ex, "work", None)
+        return float(f(r)) if f is not None else 1.0
+
+    def _pick(self, active):
+        """The requests this tick advances (in admission order)."""
+        if self.policy == "all":
+            return list(active)
+        order = sorted(active, key=lambda r: ((r.n_iter - r.iters_done) * self._work(r), r.arrival, r.rid))
+        chosen, total = [], 0.0
+        for r in order:
+            if chosen and total + self._work(r) > self.tick_work:
+                break
+            chosen.append(r)
+            total += self._work(r)
+        keep = {id(r) for r in chosen}
+        return [r for r in active if id(r) in keep]
 
     def _release(self, r):
         try:
@@ -172,6 +201,11 @@ class GpuExecutor:
             inp["footprint"] = int(inp["proj"].nbytes + 2 * 4 * nvox + plan.workspace_bytes + (1 << 20))
             plan.close()
         return inp["footprint"]
+
+    def work(self, r):
+        """Voxel-view updates of one iteration (the scheduler's unit of work)."""
+        g = self._inputs(r)["geometry"]
+        return float(g.nx) * g.ny * g.nz * g.n_views
 
     def admit(self, r):
         from .autograd import Backprojector
@@ -291,6 +325,9 @@ def main(argv=None):
     ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--skip-sequential", action="store_true")
+    ap.add_argument("--policy", choices=("all", "srpt", "both"), default="both",
+                    help="which active requests a tick advances (both: run the two policies)")
+    ap.add_argument("--tick-work", type=float, default=8e9, help="srpt: voxel-view updates per tick")
     args = ap.parse_args(argv)
 
     spec = poisson_requests(args.requests, args.rate, args.seed, args.iters)
@@ -317,14 +354,20 @@ def main(argv=None):
 
     out = dict(requests=args.requests, rate_per_s=args.rate, iters=args.iters, seed=args.seed,
                sizes={s: sum(1 for x in spec if x[2] == s) for s in SERVE_SIZES})
-    srv = Server(GpuExecutor(), int(args.budget_gb * 1e9), args.max_active)
-    reqs = srv.run(fresh())
-    out["batched"] = summarize(reqs)
-    out["batched"]["mean_batch"] = float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0
-    out["batched"]["rpe_final_mm_mean"] = float(np.mean([
-        reprojection_error(inputs[r.rid]["P"], r.result["theta"], inputs[r.rid]["theta_true"],
-                           _pitch(inputs[r.rid]["size"])) for r in reqs if r.status == "done"]))
-    print("serve: batched %s" % json.dumps(out["batched"]), flush=True)
+    policies = ("all", "srpt") if args.policy == "both" else (args.policy,)
+    runs = {}
+    for pol in policies:
+        srv = Server(GpuExecutor(), int(args.budget_gb * 1e9), args.max_active, policy=pol, tick_work=args.tick_work)
+        reqs = srv.run(fresh())
+        key = "batched" if pol == "all" else "batched_" + pol
+        out[key] = summarize(reqs)
+        out[key]["policy"] = pol
+        out[key]["mean_batch"] = float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0
+        out[key]["rpe_final_mm_mean"] = float(np.mean([
+            reprojection_error(inputs[r.rid]["P"], r.result["theta"], inputs[r.rid]["theta_true"],
+                               _pitch(inputs[r.rid]["size"])) for r in reqs if r.status == "done"]))
+        runs[pol] = reqs
+        print("serve: %s %s" % (key, json.dumps(out[key])), flush=True)
     if not args.skip_sequential:
         print("serve: sequential plain solves", flush=True)
         seq = run_sequential(fresh())
@@ -338,6 +381,7 @@ def main(argv=None):
         out["sequential"]["mean_service_s"] = service
         out["offered_load_rho"] = args.rate * service
         same = all(np.array_equal(a.result["coeffs"], b.result["coeffs"])
+                   for reqs in runs.values()
                    for a, b in zip(sorted(reqs, key=lambda r: r.rid), sorted(seq, key=lambda r: r.rid))
                    if a.status == "done")
         out["identical_results"] = bool(same)

@@ -76,10 +76,12 @@ def _req_inputs(i):
     return dict(geometry=g, proj=c.proj, P=c.P, n_nodes=cfg.n_nodes)
 
 
-def test_served_results_equal_solo_solves():
+@pytest.mark.parametrize("policy", ["all", "srpt"])
+def test_served_results_equal_solo_solves(policy):
     inputs = [_req_inputs(i) for i in range(4)]
     reqs = [Request(i, 0.0 if i < 2 else 0.002 * i, 6 + i, dict(inputs[i])) for i in range(4)]
-    srv = Server(GpuExecutor(), hbm_budget_bytes=int(50e9), max_active=3)
+    # srpt with a tick budget of about two of these requests: some ticks share launches, some not
+    srv = Server(GpuExecutor(), hbm_budget_bytes=int(50e9), max_active=3, policy=policy, tick_work=2.6e7)
     done = srv.run(reqs)
     s = summarize(done)
     print("[serve] %s mean batch %.2f" % (s, np.mean(srv.batch_sizes)), flush=True)

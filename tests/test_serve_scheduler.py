@@ -29,6 +29,9 @@ class FakeExecutor:
     def footprint(self, r):
         return r.inputs["bytes"]
 
+    def work(self, r):
+        return r.inputs.get("work", 1.0)
+
     def admit(self, r):
         if r.rid in self.fail_admit:
             raise RuntimeError("bad geometry")
@@ -124,3 +127,47 @@ def test_poisson_stream_is_seeded():
     # mean inter-arrival close to 1 / rate
     assert abs((arr[-1] / 63) - 0.5) < 0.2
     assert {x[2] for x in a} == {"serve128", "serve256", "serve384"}
+
+
+def _srpt_case(policy):
+    clk = FakeClock()
+    ex = FakeExecutor(clk, tick=0.1)
+    srv = Server(ex, hbm_budget_bytes=1000, max_active=8, clock=clk, sleep=clk.sleep, policy=policy, tick_work=2.0)
+    reqs = [Request(0, 0.0, 5, {"bytes": 10, "work": 10.0}), Request(1, 0.0, 3, {"bytes": 10, "work": 1.0}),
+            Request(2, 0.0, 2, {"bytes": 10, "work": 1.0})]
+    return srv.run(reqs), ex, srv
+
+
+def test_srpt_advances_the_least_remaining_work_first():
+    reqs, ex, srv = _srpt_case("srpt")
+    steps = [e[1] for e in ex.log if e[0] == "step"]
+    # the two small requests share ticks until they are done, then the large one runs alone
+    assert steps == [(1, 2), (1, 2), (1,), (0,), (0,), (0,), (0,), (0,)]
+    assert all(r.status == "done" and r.iters_done == r.n_iter for r in reqs)
+    done = {r.rid: r.t_done for r in reqs}
+    assert done[2] < done[1] < done[0]
+    assert srv.used == 0 and not ex.resident
+
+
+def test_processor_sharing_advances_every_active_request():
+    reqs, ex, _ = _srpt_case("all")
+    steps = [e[1] for e in ex.log if e[0] == "step"]
+    assert steps[:2] == [(0, 1, 2), (0, 1, 2)] and steps[2] == (0, 1)
+    assert all(r.status == "done" for r in reqs)
+    assert [r.result for r in reqs] == [r.result for r in _srpt_case("srpt")[0]]
+
+
+def test_srpt_lets_a_large_request_through_when_nothing_smaller_waits():
+    clk = FakeClock()
+    ex = FakeExecutor(clk, tick=0.1)
+    srv = Server(ex, hbm_budget_bytes=1000, max_active=8, clock=clk, sleep=clk.sleep, policy="srpt", tick_work=2.0)
+    reqs = srv.run([Request(0, 0.0, 2, {"bytes": 10, "work": 10.0}), Request(1, 0.05, 1, {"bytes": 10, "work": 1.0})])
+    steps = [e[1] for e in ex.log if e[0] == "step"]
+    # 0 starts alone; 1 arrives during the first tick and overtakes at the next one
+    assert steps == [(0,), (1,), (0,)]
+    assert all(r.status == "done" for r in reqs)
+
+
+def test_unknown_policy_is_rejected():
+    with pytest.raises(ValueError):
+        Server(FakeExecutor(FakeClock()), 100, policy="lifo")
