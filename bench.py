@@ -31,6 +31,8 @@ FLOPS_FWD = 23
 FLOPS_VJP = 66
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (published)
 PEAK_HBM_GBS = 8000.0
+LDS_BYTES_PER_UPDATE = 64     # 4 taps forward + 12-tap neighbourhood VJP, 4 B each
+PEAK_LDS_TBPS = 128 * 256 * 2.4e9 / 1e12   # 128 B/clk/CU (CDNA3 figure) x 256 CUs x 2.4 GHz
 # HBM bytes per launch of the dominant kernel, from the FETCH_SIZE / WRITE_SIZE counters of
 # two rocprofv3 --pmc runs of this script, scaled by the same counters read for a plain
 # elementwise kernel of known size (--copy-calib-mib). Valid only for the kernel source the
@@ -88,32 +90,62 @@ def copy_calibration(mib):
     del src, dst
 
 
-def cpu_baseline(case, n_views_sample):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(case, n_views_sample, n_views_single=4):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload: forward and
-    VJP over the whole grid for the first n_views_sample views."""
+    VJP over the whole grid for the first n_views_sample views on every OpenMP thread, and the
+    same for n_views_single views on one thread (scaling)."""
+    import ctypes
     import dataclasses
 
     import numpy as np
 
     import oracle
 
-    scan = dataclasses.replace(case.scan, n_views=n_views_sample)
-    geo = oracle.geom_from(scan, case.grid, "fdk", "paper")
-    Phat, dPhat = oracle.compose(case.theta_true[:n_views_sample], case.P[:n_views_sample])
-    proj = np.ascontiguousarray(case.proj[:n_views_sample])
     rng = np.random.default_rng(99)
     delta = rng.standard_normal(case.grid.shape)
-    t0 = time.perf_counter()
-    oracle.backproject(geo, proj, Phat)
-    t1 = time.perf_counter()
-    G = oracle.vjp(geo, proj, Phat, delta)
-    oracle.chain(G, dPhat)
-    t2 = time.perf_counter()
-    updates = case.grid.n_voxels * n_views_sample
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": updates / (t2 - t0) / 1e9, "unit": "GUPS", "cores": threads, "kind": "oracle",
-            "sample": "FP64 oracle forward (%.1f s) + VJP with chain (%.1f s) over the full %s grid for %d of %d views"
-                      % (t1 - t0, t2 - t1, "x".join(map(str, case.grid.shape)), n_views_sample, case.scan.n_views)}
+    gomp = ctypes.CDLL("libgomp.so.1")
+
+    def run(nv):
+        scan = dataclasses.replace(case.scan, n_views=nv)
+        geo = oracle.geom_from(scan, case.grid, "fdk", "paper")
+        Phat, dPhat = oracle.compose(case.theta_true[:nv], case.P[:nv])
+        proj = np.ascontiguousarray(case.proj[:nv])
+        t0 = time.perf_counter()
+        oracle.backproject(geo, proj, Phat)
+        t1 = time.perf_counter()
+        G = oracle.vjp(geo, proj, Phat, delta)
+        oracle.chain(G, dPhat)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, case.grid.n_voxels * nv
+
+    oracle.build()
+    threads = int(gomp.omp_get_max_threads())
+    tf, tv, upd = run(n_views_sample)
+    out = {"value": upd / (tf + tv) / 1e9, "unit": "GUPS", "cores": threads, "kind": "oracle",
+           "sample": "FP64 oracle forward (%.1f s) + VJP with chain (%.1f s) over the full %s grid for %d of %d views"
+                     % (tf, tv, "x".join(map(str, case.grid.shape)), n_views_sample, case.scan.n_views),
+           "gups_forward": upd / tf / 1e9, "gups_vjp": upd / tv / 1e9, "cpu_model": _cpu_model()}
+    if n_views_single > 0:
+        gomp.omp_set_num_threads(1)
+        try:
+            sf, sv, supd = run(n_views_single)
+        finally:
+            gomp.omp_set_num_threads(threads)
+        out["single_thread"] = {"value": supd / (sf + sv) / 1e9, "unit": "GUPS", "cores": 1,
+                                "sample": "forward + VJP with chain over the full grid for %d views (%.1f s)"
+                                          % (n_views_single, sf + sv)}
+    return out
 
 
 def main():
@@ -124,6 +156,8 @@ def main():
     ap.add_argument("--config", default="head256")
     ap.add_argument("--lr", type=float, default=0.05)
     ap.add_argument("--cpu-views", type=int, default=160, help="views of the oracle's bounded CPU sample")
+    ap.add_argument("--cpu-single-views", type=int, default=4,
+                    help="views of the oracle's single-thread sample (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one elementwise kernel over this many MiB first (HBM counter calibration)")
@@ -228,13 +262,25 @@ def main():
             "gups_fwd_plus_jacobian": upd / ((fwd_ms + vjp_ms) * 1e-3) / 1e9,
             "forward_tflops": FLOPS_FWD * upd / (fwd_ms * 1e-3) / 1e12,
         },
+        "context": {
+            # both passes at the method's 89 flops per update, against the packed and the
+            # non-packed FP32 vector peak; LDS at the algorithmic 64 B of tap reads per update
+            # against 128 B/clk/CU x 256 CUs x 2.4 GHz
+            "fwd_plus_vjp_tflops": (FLOPS_FWD + FLOPS_VJP) * upd / ((fwd_ms + vjp_ms) * 1e-3) / 1e12,
+            "frac_fp32_peak": (FLOPS_FWD + FLOPS_VJP) * upd / ((fwd_ms + vjp_ms) * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+            "frac_fp32_nonpacked": (FLOPS_FWD + FLOPS_VJP) * upd / ((fwd_ms + vjp_ms) * 1e-3) / 1e12
+                                   / (PEAK_FP32_TFLOPS / 2),
+            "lds_tb_per_s": LDS_BYTES_PER_UPDATE * upd / ((fwd_ms + vjp_ms) * 1e-3) / 1e12,
+            "frac_lds_peak": LDS_BYTES_PER_UPDATE * upd / ((fwd_ms + vjp_ms) * 1e-3) / 1e12 / PEAK_LDS_TBPS,
+            "vjp_hbm_tb_per_s": (traffic["bytes"] / (vjp_ms * 1e-3) / 1e12) if traffic else None,
+        },
         "latency_ms": {"step_p50": percentile(t_stp, 50), "step_p99": percentile(t_stp, 99)},
         "peak_hbm_gb": torch.cuda.max_memory_allocated() / 1e9,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on %d views" % args.cpu_views, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_views)
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_views, args.cpu_single_views)
     print(json.dumps(out), flush=True)
 
 

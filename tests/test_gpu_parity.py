@@ -162,6 +162,50 @@ def test_ragged_grid_and_detector_edges():
             assert np.all(eg <= GRAD_TOL)
 
 
+def test_oversized_tiles_gather_from_global_memory():
+    """A fine detector (0.05 mm pixels): every brick's tile is hundreds of pixels wide, beyond
+    every LDS tile and beyond the descriptor's 8-bit extent fields, so all taps come from the
+    global-memory sampler; the volume is wider than the field of view."""
+    scan = ScanGeometry(n_views=12, det_w=600, det_h=400, pitch_mm=0.05)
+    grid = VolumeGrid(24, 24, 16, (1.0, 1.0, 1.0))
+    rng = np.random.default_rng(31)
+    P = projection_matrices(scan)
+    th = np.concatenate([rng.uniform(-1, 1, (scan.n_views, 3)), rng.uniform(-0.02, 0.02, (scan.n_views, 3))], 1)
+    # a detector this fine oversamples the image: white noise smoothed by [1 2 1]/4 twice per axis
+    # (FP32 tile-local positions reach ~500 px here, so the error scales with the per-pixel slope)
+    proj = rng.standard_normal((scan.n_views, scan.det_h, scan.det_w))
+    for ax in (1, 2):
+        for _ in range(2):
+            proj = 0.5 * proj + 0.25 * (np.roll(proj, 1, ax) + np.roll(proj, -1, ax))
+    proj = proj.astype(np.float32)
+    delta = rng.standard_normal(grid.shape).astype(np.float32)
+    s = Setup(scan, grid, P, th, proj, "fdk")
+    ev = vol_err(s.fwd(), oracle.backproject(s.geo, proj, s.Phat))
+    g, _ = s.vjp(delta)
+    eg = grad_err(g, oracle.chain(oracle.vjp(s.geo, proj, s.Phat, delta), s.dPhat))
+    _report("oversized tiles", vol=ev, grad=np.array2string(eg, precision=2))
+    assert ev <= VOL_TOL
+    assert np.all(eg <= GRAD_TOL)
+
+
+def test_volume_outside_the_beam_is_zero():
+    """Motion that lifts the whole volume 400 mm along z: nothing projects onto the detector,
+    every (view, brick) pair is skipped, the volume and every gradient are exactly zero."""
+    scan = ScanGeometry(n_views=20, det_w=64, det_h=48, pitch_mm=1.0)
+    grid = VolumeGrid(20, 18, 17, (1.0, 1.0, 1.0))
+    P = projection_matrices(scan)
+    th = np.zeros((scan.n_views, 6))
+    th[:, 2] = 400.0
+    rng = np.random.default_rng(5)
+    proj = rng.standard_normal((scan.n_views, scan.det_h, scan.det_w)).astype(np.float32)
+    s = Setup(scan, grid, P, th, proj, "fdk")
+    assert not np.any(oracle.backproject(s.geo, proj, s.Phat))
+    assert not np.any(s.fwd())
+    g, gP = s.vjp(rng.standard_normal(grid.shape).astype(np.float32))
+    assert not np.any(g) and not np.any(gP)
+    s.bp.check()
+
+
 def test_single_voxel_and_single_view():
     scan = ScanGeometry(n_views=1, det_w=9, det_h=7, pitch_mm=1.0)
     grid = VolumeGrid(1, 1, 1, (1.0, 1.0, 1.0))
