@@ -288,7 +288,8 @@ __device__ __forceinline__ void taps_masked(LdsF* b, float au, float av, float2 
 // Per view v the workgroup (1) waits for its tile of view v (issued one view earlier into the
 // other LDS buffer) and synchronises, (2) issues the asynchronous global->LDS loads of view
 // v+1's tile, and the border tables of view v+1 if that tile crosses the detector border,
-// (3) samples view v from LDS while those loads are in flight. Tiles are filled with clamped
+// (3) samples view v from LDS while those loads are in flight. A single-buffered (large) tile
+// instead synchronises after (3) and only then issues view v+1's loads. Tiles are filled with clamped
 // detector coordinates (the border pixel repeats outside the detector); the interior path
 // never touches the repeats, the border path masks them with the tables:
 //   column table (z, s): z = 1 inside the detector, 0 outside (bilinear taps of d, g_v);
@@ -310,6 +311,11 @@ __device__ __forceinline__ BrickDesc load_desc(const __attribute__((address_spac
     return d;
 }
 
+// Detector-tile buffers per workgroup: two while two tiles leave room for six workgroups per
+// CU (the next view's tile loads then overlap the current view's samples); larger tiles are
+// single-buffered so that four workgroups fit, and the overlap comes from the other workgroups.
+constexpr int tile_buffers(int plane) { return plane <= 80 * 36 ? 2 : 1; }
+
 // The work of one item (a brick and a contiguous chunk of its views); shared by the
 // single-plan kernel and the batched one. Item q is brick q % n_bricks and chunk q / n_bricks;
 // chunk c covers views [c n / vsplit, (c + 1) n / vsplit). The forward of chunk 0 writes the
@@ -322,6 +328,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                                          float* __restrict__ sT, float2* __restrict__ sCol, float2* __restrict__ sRow,
                                          float* __restrict__ sRed) {
     constexpr int PLANE = TP * TH;
+    constexpr int NB = tile_buffers(PLANE);
     constexpr int NSEG = (TP + 63) / 64;
     static_assert(BZ % 8 == 0, "the forward samples a column in groups of 8");
     const int brick = item % a.n_bricks, chunk = item / a.n_bricks;
@@ -423,13 +430,13 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
     BrickDesc cur;
     if (v_lo < v_hi) {
         cur = load_desc(descs + (long long)v_lo * dstride);
-        stage(cur, v_lo, v_lo & 1);
+        stage(cur, v_lo, NB == 2 ? (v_lo & 1) : 0);
     }
     int prev_ou = 0, prev_ov = 0;
     for (int v = v_lo; v < v_hi; ++v) {
-        const int buf = v & 1;
+        const int buf = NB == 2 ? (v & 1) : 0;
         __builtin_amdgcn_s_waitcnt(0);   // this wave's tile loads of view v have landed in LDS
-        __syncthreads();                 // ... and everybody's; buffer buf^1 is free again
+        __syncthreads();                 // ... and everybody's; a second buffer is free again
         if (VJP && v > v_lo && t < 14) {
             float s;
             if (t < 12) {
@@ -441,7 +448,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
             part[((long long)(v - 1) * a.n_bricks + brick) * PART_STRIDE + t] = s;
         }
         BrickDesc nxt;
-        if (v + 1 < v_hi) {
+        if (NB == 2 && v + 1 < v_hi) {
             nxt = load_desc(descs + (long long)(v + 1) * dstride);
             stage(nxt, v + 1, buf ^ 1);
         }
@@ -613,7 +620,15 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                 rb[2] = red[2];
             }
         }
-        if (v + 1 < v_hi) cur = nxt;
+        if (v + 1 < v_hi) {
+            if (NB == 1) {
+                // single buffer: everybody has finished sampling view v before it is overwritten
+                nxt = load_desc(descs + (long long)(v + 1) * dstride);
+                __syncthreads();
+                stage(nxt, v + 1, 0);
+            }
+            cur = nxt;
+        }
     }
 
     if (VJP) {
@@ -639,14 +654,14 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
 
 template <int TP, int TH>
 struct BpShared {
-    float sT[2 * TP * TH];
-    float2 sCol[2 * TP];
-    float2 sRow[2 * TH];
+    float sT[tile_buffers(TP * TH) * TP * TH];
+    float2 sCol[tile_buffers(TP * TH) * TP];
+    float2 sRow[tile_buffers(TP * TH) * TH];
     float sRed[2 * 4 * 12];
 };
 
-// workgroups per CU the register budget is sized for: as many as the LDS tile allows
-constexpr int bp_occupancy(int plane) { return plane <= 80 * 36 ? 6 : (plane <= 128 * 64 ? 2 : 1); }
+// workgroups per CU the register budget is sized for: as many as the LDS tiles allow
+constexpr int bp_occupancy(int plane) { return plane <= 80 * 36 ? 6 : (plane <= 128 * 64 ? 4 : 1); }
 
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
 __global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH))

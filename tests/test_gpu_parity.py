@@ -162,6 +162,28 @@ def test_ragged_grid_and_detector_edges():
             assert np.all(eg <= GRAD_TOL)
 
 
+@pytest.mark.parametrize("flags", [0, gmc.FLAG_FORCE_EDGE])
+def test_coarse_voxels_on_a_fine_detector(flags):
+    """2 mm voxels on the 700 x 500 detector at 0.64 mm over a full circle: the plan takes the
+    largest (single-buffered) tile; ragged grid, volume wider than the detector's reach in z."""
+    scan = ScanGeometry(n_views=23, det_w=700, det_h=500, pitch_mm=0.64, arc_deg=360.0)
+    grid = VolumeGrid(40, 36, 120, (2.0, 2.0, 2.0))
+    rng = np.random.default_rng(41)
+    P = projection_matrices(scan)
+    th = np.concatenate([rng.uniform(-5, 5, (scan.n_views, 3)), rng.uniform(-0.08, 0.08, (scan.n_views, 3))], 1)
+    proj = rng.standard_normal((scan.n_views, scan.det_h, scan.det_w)).astype(np.float32)
+    delta = rng.standard_normal(grid.shape).astype(np.float32)
+    for weighting in ("fdk", "paper"):
+        s = Setup(scan, grid, P, th, proj, weighting, flags=flags)
+        assert s.bp.plan.info()["tile_pitch"] == 128
+        ev = vol_err(s.fwd(), oracle.backproject(s.geo, proj, s.Phat))
+        g, _ = s.vjp(delta)
+        eg = grad_err(g, oracle.chain(oracle.vjp(s.geo, proj, s.Phat, delta), s.dPhat))
+        _report("coarse voxels", weighting=weighting, flags=flags, vol=ev, grad=np.array2string(eg, precision=2))
+        assert ev <= VOL_TOL
+        assert np.all(eg <= GRAD_TOL)
+
+
 def test_oversized_tiles_gather_from_global_memory():
     """A fine detector (0.05 mm pixels): every brick's tile is hundreds of pixels wide, beyond
     every LDS tile and beyond the descriptor's 8-bit extent fields, so all taps come from the
