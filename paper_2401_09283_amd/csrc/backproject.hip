@@ -130,6 +130,7 @@ __device__ __forceinline__ Smp next_sample(Column& c, int k) {
 // fraction is 1 and the bilinear value is the same). Every sample of a tile has tile
 // coordinates >= 1 (the tile origin lies two pixels below the smallest projected corner).
 constexpr int VJP_GROUP = 1;          // VJP samples whose LDS reads are issued together
+constexpr int FWD_GROUP = 4;          // forward samples whose LDS reads are issued together
 constexpr float RND23 = 8388607.5f;   // 2^23 - 1/2
 constexpr float TWO23 = 8388608.0f;   // 2^23
 
@@ -285,11 +286,12 @@ __device__ __forceinline__ void taps_masked(LdsF* b, float au, float av, float2 
 
 // ---------------------------------------------------------------- the kernel
 //
-// Per view v the workgroup (1) waits for its tile of view v (issued one view earlier into the
-// other LDS buffer) and synchronises, (2) issues the asynchronous global->LDS loads of view
-// v+1's tile, and the border tables of view v+1 if that tile crosses the detector border,
-// (3) samples view v from LDS while those loads are in flight. A single-buffered (large) tile
-// instead synchronises after (3) and only then issues view v+1's loads. Tiles are filled with clamped
+// Per view v the workgroup (1) waits for its tile of view v and synchronises, (2) samples view
+// v from LDS, (3) synchronises again and issues the asynchronous global->LDS loads of view
+// v+1's tile into the same buffer, and the border tables of view v+1 if that tile crosses the
+// detector border. The tile loads of one workgroup overlap the sampling of the others on the
+// CU: with one buffer per workgroup, more workgroups fit (measured faster than two buffers per
+// workgroup with the next tile's loads in flight during the sampling). Tiles are filled with clamped
 // detector coordinates (the border pixel repeats outside the detector); the interior path
 // never touches the repeats, the border path masks them with the tables:
 //   column table (z, s): z = 1 inside the detector, 0 outside (bilinear taps of d, g_v);
@@ -311,11 +313,6 @@ __device__ __forceinline__ BrickDesc load_desc(const __attribute__((address_spac
     return d;
 }
 
-// Detector-tile buffers per workgroup: two while two tiles leave room for six workgroups per
-// CU (the next view's tile loads then overlap the current view's samples); larger tiles are
-// single-buffered so that four workgroups fit, and the overlap comes from the other workgroups.
-constexpr int tile_buffers(int plane) { return plane <= 80 * 36 ? 2 : 1; }
-
 // The work of one item (a brick and a contiguous chunk of its views); shared by the
 // single-plan kernel and the batched one. Item q is brick q % n_bricks and chunk q / n_bricks;
 // chunk c covers views [c n / vsplit, (c + 1) n / vsplit). The forward of chunk 0 writes the
@@ -327,10 +324,8 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                                          const float* __restrict__ gvol, float* __restrict__ part, const int item,
                                          float* __restrict__ sT, float2* __restrict__ sCol, float2* __restrict__ sRow,
                                          float* __restrict__ sRed) {
-    constexpr int PLANE = TP * TH;
-    constexpr int NB = tile_buffers(PLANE);
     constexpr int NSEG = (TP + 63) / 64;
-    static_assert(BZ % 8 == 0, "the forward samples a column in groups of 8");
+    static_assert(BZ % FWD_GROUP == 0, "the forward samples a column in whole groups");
     const int brick = item % a.n_bricks, chunk = item / a.n_bricks;
     const int v_lo = chunk * a.n_views / a.vsplit, v_hi = (chunk + 1) * a.n_views / a.vsplit;
     const int bj = brick % a.nby;
@@ -380,22 +375,25 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
     ConstDesc* descs = (ConstDesc*)(desc + brick);
     const long long dstride = a.n_bricks;
 
-    // Issue view vv's tile loads into buffer buf (asynchronous, no registers). Rows are
+    // Issue view vv's tile loads (asynchronous, no registers). Rows are
     // distributed over the four waves and walked with scalar registers; each lane carries one
     // clamped detector column per 64-column segment, lanes outside the tile's columns are masked
     // once per segment. Interior tiles need no row clamp and step their row address by four rows.
     const int wv = __builtin_amdgcn_readfirstlane(wave);
-    auto stage = [&](const BrickDesc& D, int vv, int buf) {
+    auto stage = [&](const BrickDesc& D, int vv) {
         if (D.mode != TILE_INTERIOR && D.mode != TILE_EDGE) return;
         const float* __restrict__ img = proj + (long long)vv * a.plane;
-        float* tile = sT + buf * PLANE;
+        float* tile = sT;
         // the VJP needs the whole tile; the forward no halo: rows and columns 1 .. extent - 2
         constexpr int H0 = VJP ? 0 : 1;
         const int c_end = D.tw - H0, r_end = D.th - H0;
+        // the lane's columns are recomputed per view rather than kept live across the sampling
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
 #pragma unroll
         for (int q = 0; q < NSEG; ++q) {
             if (q * 64 >= c_end) break;
-            const int c = q * 64 + lane;
+            const int c = q * 64 + ln;
             const unsigned cb = 4u * (unsigned)min(max(D.ou + c, 0), a.W - 1);
             if (c >= H0 && c < c_end) {   // lanes outside the tile's columns stay idle
                 if (D.mode == TILE_INTERIOR) {
@@ -417,12 +415,12 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                 const int gc = D.ou + t;
                 const float z = ((unsigned)gc < (unsigned)a.W) ? 1.0f : 0.0f;
                 const float sg = (gc == 0 || gc == a.W - 1) ? 2.0f : 1.0f;
-                sCol[buf * TP + t] = make_float2(z, sg);
+                sCol[t] = make_float2(z, sg);
             } else if (t >= 128 && t < 128 + TH) {
                 const int gr = D.ov + (t - 128);
                 const float z = ((unsigned)gr < (unsigned)a.H) ? 1.0f : 0.0f;
                 const float sg = (gr == 0 || gr == a.H - 1) ? 2.0f : 1.0f;
-                sRow[buf * TH + (t - 128)] = make_float2(z, sg);
+                sRow[t - 128] = make_float2(z, sg);
             }
         }
     };
@@ -430,13 +428,12 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
     BrickDesc cur;
     if (v_lo < v_hi) {
         cur = load_desc(descs + (long long)v_lo * dstride);
-        stage(cur, v_lo, NB == 2 ? (v_lo & 1) : 0);
+        stage(cur, v_lo);
     }
     int prev_ou = 0, prev_ov = 0;
     for (int v = v_lo; v < v_hi; ++v) {
-        const int buf = NB == 2 ? (v & 1) : 0;
         __builtin_amdgcn_s_waitcnt(0);   // this wave's tile loads of view v have landed in LDS
-        __syncthreads();                 // ... and everybody's; a second buffer is free again
+        __syncthreads();                 // ... and everybody's
         if (VJP && v > v_lo && t < 14) {
             float s;
             if (t < 12) {
@@ -446,11 +443,6 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                 s = __int_as_float(t == 12 ? prev_ou : prev_ov);
             }
             part[((long long)(v - 1) * a.n_bricks + brick) * PART_STRIDE + t] = s;
-        }
-        BrickDesc nxt;
-        if (NB == 2 && v + 1 < v_hi) {
-            nxt = load_desc(descs + (long long)(v + 1) * dstride);
-            stage(nxt, v + 1, buf ^ 1);
         }
         prev_ou = cur.ou;
         prev_ov = cur.ov;
@@ -464,7 +456,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
         col.du = m[2] * dz;
         col.dv = m[6] * dz;
         col.dw = m[10] * dz;
-        const float* tile = sT + buf * PLANE;
+        const float* tile = sT;
         const float cmax = (float)(cur.tw - 3), rmax = (float)(cur.th - 3);
 
         if (cur.mode == TILE_INTERIOR) {
@@ -472,14 +464,14 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
             const float lo = (float)(TP + 1), hi = fmaf(rmax, (float)TP, cmax);
             const unsigned base = lds_base(tile, 4u);
             if (!VJP) {
-                // per group of 8 samples: positions first, then all LDS reads, then the
+                // per group of FWD_GROUP samples: positions first, then all LDS reads, then the
                 // arithmetic, so that the reads of a group are in flight together
 #pragma unroll
-                for (int g = 0; g < BZ; g += 8) {
-                    unsigned off[8];
-                    float au[8], av[8], ww[8];
+                for (int g = 0; g < BZ; g += FWD_GROUP) {
+                    unsigned off[FWD_GROUP];
+                    float au[FWD_GROUP], av[FWD_GROUP], ww[FWD_GROUP];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
+                    for (int k = 0; k < FWD_GROUP; ++k) {
                         const Smp p = next_sample(col, g + k);
                         const Cell c = cell_of(p);
                         off[k] = tile_cell<TP>(c, lo, hi, base);
@@ -487,9 +479,9 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                         av[k] = c.av;
                         ww[k] = (WEIGHT == GMC_WEIGHT_FDK) ? p.rw * p.rw : 1.0f;
                     }
-                    float d00[8], d01[8], d10[8], d11[8];
+                    float d00[FWD_GROUP], d01[FWD_GROUP], d10[FWD_GROUP], d11[FWD_GROUP];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
+                    for (int k = 0; k < FWD_GROUP; ++k) {
                         LdsF* b = lds_f(off[k]);
                         d00[k] = b[0];
                         d01[k] = b[1];
@@ -497,7 +489,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                         d11[k] = b[TP + 1];
                     }
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
+                    for (int k = 0; k < FWD_GROUP; ++k) {
                         const float top = lerp(d00[k], d01[k], au[k]);
                         const float bot = lerp(d10[k], d11[k], au[k]);
                         const float val = lerp(top, bot, av[k]);
@@ -533,7 +525,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
             // per slice k (uniform branches): skip slices that miss the detector, plain taps for
             // slices inside it, masked taps for the slices across its border
             const float lo = (float)(TP + 1), hi = fmaf(rmax, (float)TP, cmax);
-            const unsigned tb = lds_base(tile, 4u), cb = lds_base(sCol + buf * TP, 8u), rb = lds_base(sRow + buf * TH, 8u);
+            const unsigned tb = lds_base(tile, 4u), cb = lds_base(sCol, 8u), rb = lds_base(sRow, 8u);
             const unsigned kin = cur.kin, kout = cur.kout;
 #pragma unroll
             for (int k = 0; k < BZ; ++k) {
@@ -621,13 +613,9 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
             }
         }
         if (v + 1 < v_hi) {
-            if (NB == 1) {
-                // single buffer: everybody has finished sampling view v before it is overwritten
-                nxt = load_desc(descs + (long long)(v + 1) * dstride);
-                __syncthreads();
-                stage(nxt, v + 1, 0);
-            }
-            cur = nxt;
+            cur = load_desc(descs + (long long)(v + 1) * dstride);
+            __syncthreads();   // everybody has finished sampling view v: the tile can be refilled
+            stage(cur, v + 1);
         }
     }
 
@@ -654,17 +642,20 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
 
 template <int TP, int TH>
 struct BpShared {
-    float sT[tile_buffers(TP * TH) * TP * TH];
-    float2 sCol[tile_buffers(TP * TH) * TP];
-    float2 sRow[tile_buffers(TP * TH) * TH];
+    float sT[TP * TH];
+    float2 sCol[TP];
+    float2 sRow[TH];
     float sRed[2 * 4 * 12];
 };
 
-// workgroups per CU the register budget is sized for: as many as the LDS tiles allow
-constexpr int bp_occupancy(int plane) { return plane <= 80 * 36 ? 6 : (plane <= 128 * 64 ? 4 : 1); }
+// Workgroups per CU the register budget is sized for. Small and middle tiles leave the
+// occupancy to the registers: 6 for the VJP (80 VGPRs; 7 would spill), 8 for the forward (60
+// VGPRs with samples read in groups of 4), the hardware's 32 waves per CU; the largest tile
+// (34 KB) fits four times.
+constexpr int bp_occupancy(int plane, bool vjp) { return plane <= 80 * 36 ? (vjp ? 6 : 8) : (plane <= 128 * 64 ? 4 : 1); }
 
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
-__global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH))
+__global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH, VJP))
     k_bp(BpArgs a, const BrickDesc* __restrict__ desc, const float* __restrict__ proj, float* __restrict__ vol,
          const float* __restrict__ gvol, float* __restrict__ part) {
     __shared__ BpShared<TP, TH> sh;
@@ -677,7 +668,7 @@ __global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH))
 // Several plans in one launch: the work items of all plans form one index space (plan q owns
 // [begin_q, begin_q + n_bricks_q vsplit_q)), mapped to XCDs like a single plan's items.
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
-__global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH)) k_bp_batch(BatchTable tab) {
+__global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH, VJP)) k_bp_batch(BatchTable tab) {
     __shared__ BpShared<TP, TH> sh;
     const int blk = blockIdx.x;
     const int g = (blk & 7) * tab.per_xcd + (blk >> 3);
