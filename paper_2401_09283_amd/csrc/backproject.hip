@@ -137,11 +137,13 @@ constexpr float TWO23 = 8388608.0f;   // 2^23
 struct Cell {
     float fu, fv;   // cell (integer-valued floats)
     float au, av;   // fractions in [0, 1]
+    float fub;      // fu + 2^23 (its bit pattern is 0x4B000000 + fu)
 };
 
 __device__ __forceinline__ Cell cell_of(const Smp& s) {
     Cell c;
-    c.fu = (s.uh + RND23) - TWO23;
+    c.fub = s.uh + RND23;
+    c.fu = c.fub - TWO23;
     c.fv = (s.vh + RND23) - TWO23;
     c.au = s.uh - c.fu;
     c.av = s.vh - c.fv;
@@ -167,10 +169,12 @@ __device__ __forceinline__ LdsF* lds_f(unsigned addr) { return (LdsF*)(size_t)ad
 
 // LDS address of the sample's cell (row-major, pitch TP), the cell clamped into [lo, hi] so
 // that every tap stays inside the tile buffer (a guard: the tile bounds already contain every
-// sample).
+// sample). The linear cell is formed with the column's 2^23 bias already in place
+// (fv TP + fu + 2^23, exact below 2^24), so its bits give the address without another add.
 template <int TP>
 __device__ __forceinline__ unsigned tile_cell(const Cell& c, float lo, float hi, unsigned base) {
-    return lds_index(base, 4u, __builtin_amdgcn_fmed3f(fmaf(c.fv, (float)TP, c.fu), lo, hi));
+    const float nb = __builtin_amdgcn_fmed3f(fmaf(c.fv, (float)TP, c.fub), lo + TWO23, hi + TWO23);
+    return base + 4u * __float_as_uint(nb);
 }
 
 // Row coefficients of Eq. 4 for one sample, accumulated into the 6 running sums of the column:
@@ -193,7 +197,11 @@ __device__ __forceinline__ void accumulate(const Smp& p, float seed, float val, 
     S0 = fmaf(e, gu, S0);
     S1 = fmaf(e, gv, S1);
     S2 = fmaf(e, tt, S2);
-    if (k < BZ - 1) {
+    if (k == 0) {   // P starts at 0: a copy, not an add (which would also turn -0 into +0)
+        T0 = S0;
+        T1 = S1;
+        T2 = S2;
+    } else if (k < BZ - 1) {
         T0 += S0;
         T1 += S1;
         T2 += S2;
