@@ -15,7 +15,9 @@ Which active requests a tick advances is the policy: ``"all"`` advances every ac
 (processor sharing), ``"srpt"`` (the default) advances the requests with the least remaining work first
 (remaining iterations times the voxel-view updates of one iteration), adding requests to the
 tick until its work reaches ``tick_work`` updates (at least one request): small requests
-share launches and finish early, a large request runs alone once nothing smaller waits.
+share launches and finish early, a large request runs alone once nothing smaller waits. With
+``max_wait`` set, requests that arrived more than ``max_wait`` seconds ago go first, oldest
+first, which bounds how long a large request can be overtaken.
 Results do not depend on the policy: every request's own iterations are the same.
 
 The scheduler is independent of the GPU: ``Server`` drives an executor with four calls
@@ -63,7 +65,7 @@ class Server:
     """Continuous batching over an executor (see module docstring)."""
 
     def __init__(self, executor, hbm_budget_bytes: int, max_active: int = 16, clock=None, sleep=None,
-                 policy: str = "srpt", tick_work: float = 8e9):
+                 policy: str = "srpt", tick_work: float = 8e9, max_wait: float | None = None):
         if policy not in ("all", "srpt"):
             raise ValueError("policy must be 'all' or 'srpt'")
         self.ex = executor
@@ -71,6 +73,8 @@ class Server:
         self.max_active = int(max_active)
         self.policy = policy
         self.tick_work = float(tick_work)
+        self.max_wait = None if max_wait is None else float(max_wait)
+        self._now = lambda: 0.0
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
         self.used = 0
@@ -83,6 +87,7 @@ class Server:
         waiting, active = [], []
         t0 = self.clock()
         now = lambda: self.clock() - t0  # noqa: E731
+        self._now = now
         while pending or waiting or active:
             t = now()
             while pending and pending[0].arrival <= t:
@@ -141,7 +146,14 @@ class Server:
         """The requests this tick advances (in admission order)."""
         if self.policy == "all":
             return list(active)
-        order = sorted(active, key=lambda r: ((r.n_iter - r.iters_done) * self._work(r), r.arrival, r.rid))
+        t = self._now()
+
+        def key(r):
+            if self.max_wait is not None and t - r.arrival > self.max_wait:
+                return (0, r.arrival, r.rid)
+            return (1, (r.n_iter - r.iters_done) * self._work(r), r.rid)
+
+        order = sorted(active, key=key)
         chosen, total = [], 0.0
         for r in order:
             if chosen and total + self._work(r) > self.tick_work:
@@ -328,6 +340,8 @@ def main(argv=None):
     ap.add_argument("--policy", choices=("all", "srpt", "both"), default="both",
                     help="which active requests a tick advances (both: run the two policies)")
     ap.add_argument("--tick-work", type=float, default=8e9, help="srpt: voxel-view updates per tick")
+    ap.add_argument("--max-wait", type=float, default=10.0,
+                    help="srpt: requests older than this many seconds go first (<= 0: never)")
     args = ap.parse_args(argv)
 
     spec = poisson_requests(args.requests, args.rate, args.seed, args.iters)
@@ -357,11 +371,14 @@ def main(argv=None):
     policies = ("all", "srpt") if args.policy == "both" else (args.policy,)
     runs = {}
     for pol in policies:
-        srv = Server(GpuExecutor(), int(args.budget_gb * 1e9), args.max_active, policy=pol, tick_work=args.tick_work)
+        srv = Server(GpuExecutor(), int(args.budget_gb * 1e9), args.max_active, policy=pol, tick_work=args.tick_work,
+                     max_wait=args.max_wait if args.max_wait > 0 else None)
         reqs = srv.run(fresh())
         key = "batched" if pol == "all" else "batched_" + pol
         out[key] = summarize(reqs)
         out[key]["policy"] = pol
+        if pol == "srpt":
+            out[key]["max_wait_s"] = args.max_wait if args.max_wait > 0 else None
         out[key]["mean_batch"] = float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0
         out[key]["rpe_final_mm_mean"] = float(np.mean([
             reprojection_error(inputs[r.rid]["P"], r.result["theta"], inputs[r.rid]["theta_true"],

@@ -171,3 +171,22 @@ def test_srpt_lets_a_large_request_through_when_nothing_smaller_waits():
 def test_unknown_policy_is_rejected():
     with pytest.raises(ValueError):
         Server(FakeExecutor(FakeClock()), 100, policy="lifo")
+
+
+def test_srpt_with_a_waiting_cap_serves_old_requests_first():
+    clk = FakeClock()
+    ex = FakeExecutor(clk, tick=0.1)
+    srv = Server(ex, hbm_budget_bytes=1000, max_active=8, clock=clk, sleep=clk.sleep, policy="srpt", tick_work=2.0,
+                 max_wait=0.25)
+    reqs = srv.run([Request(0, 0.0, 3, {"bytes": 10, "work": 10.0}), Request(1, 0.05, 6, {"bytes": 10, "work": 1.0})])
+    steps = [e[1] for e in ex.log if e[0] == "step"]
+    # 1 overtakes 0 at the second tick, until 0 has waited more than 0.25 s; then 0 goes first
+    assert steps[:3] == [(0,), (1,), (1,)]
+    assert steps[3] == (0,)
+    assert all(r.status == "done" and r.iters_done == r.n_iter for r in reqs)
+    # without the cap, 0 waits until 1 is done
+    clk2 = FakeClock()
+    ex2 = FakeExecutor(clk2, tick=0.1)
+    Server(ex2, 1000, 8, clock=clk2, sleep=clk2.sleep, policy="srpt", tick_work=2.0).run(
+        [Request(0, 0.0, 3, {"bytes": 10, "work": 10.0}), Request(1, 0.05, 6, {"bytes": 10, "work": 1.0})])
+    assert [e[1] for e in ex2.log if e[0] == "step"] == [(0,)] + [(1,)] * 6 + [(0,), (0,)]
