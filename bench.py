@@ -52,12 +52,18 @@ def percentile(xs, q):
 
 
 def kernel_source_hash():
+    """Hash of the backprojection kernel's code: its sources with comments and whitespace
+    removed, so that an edit of a comment does not invalidate recorded counters."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

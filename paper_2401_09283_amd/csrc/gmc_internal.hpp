@@ -11,7 +11,8 @@ namespace gmc {
 
 // Voxel bricks are BXY x BXY columns of BRICK_Z voxels; one workgroup of BXY*BXY threads
 // owns a brick and each thread owns one column (a run of BRICK_Z voxels along z). Shallow
-// bricks keep the detector tile small (six workgroups per CU).
+// bricks keep the detector tile small: the tile the brick projects to is staged in LDS once
+// per view, and a small tile leaves the workgroups per CU to the register budget.
 constexpr int BXY = 16;
 constexpr int BRICK_Z = 8;
 constexpr int THREADS = BXY * BXY;
@@ -42,12 +43,14 @@ static_assert(sizeof(BrickDesc) == 64, "descriptor must be 64 bytes");
 // the tile origin (ou, ov) as int bits, then 2 unused slots.
 constexpr int PART_STRIDE = 16;
 
-// Tile configurations (pitch TP floats, TH rows per plane) compiled into the kernels. Two
-// planes of 80 x 36 floats plus the border tables fit six workgroups into the 160 KB of LDS of
-// a CU; a brick of 16 x 16 x 8 voxels at 1 mm in the 200-degree scan geometry projects to at
-// most about 74 x 38 pixels, and a tile that exceeds the plan's configuration is sampled from
-// global memory instead. A row pitch of 80 floats (16 banks apart modulo 32) spreads the
-// neighbouring rows a wavefront reads over different LDS banks.
+// Tile configurations (pitch TP floats, TH rows) compiled into the kernels; one tile per
+// workgroup. 80 x 36 floats plus the border tables take 12.8 KB (the registers, not the 160 KB
+// of LDS, then bound the workgroups per CU); a brick of 16 x 16 x 8 voxels at 1 mm in the
+// 200-degree scan geometry projects to at most about 74 x 38 pixels, and a tile that exceeds
+// the plan's configuration is sampled from global memory instead. 128 x 64 (34.7 KB, four
+// workgroups per CU) serves coarse voxels on a fine detector. A row pitch of 80 floats (16
+// banks apart modulo 32) spreads the neighbouring rows a wavefront reads over different LDS
+// banks.
 struct TileCfg {
     int tp, th;
 };
