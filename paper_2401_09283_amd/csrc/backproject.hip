@@ -334,6 +334,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                                          float* __restrict__ sRed) {
     constexpr int NSEG = (TP + 63) / 64;
     static_assert(BZ % FWD_GROUP == 0, "the forward samples a column in whole groups");
+    static_assert(TP <= 128 && 128 + TH <= THREADS, "border tables: columns by threads 0 .. TP-1, rows by 128 ..");
     const int brick = item % a.n_bricks, chunk = item / a.n_bricks;
     const int v_lo = chunk * a.n_views / a.vsplit, v_hi = (chunk + 1) * a.n_views / a.vsplit;
     const int bj = brick % a.nby;

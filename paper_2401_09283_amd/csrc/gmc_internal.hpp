@@ -55,7 +55,6 @@ struct TileCfg {
     int tp, th;
 };
 constexpr TileCfg TILE_CFGS[] = {{40, 40}, {80, 36}, {128, 64}};
-constexpr int TILE_CFG_MAX_TP = 128;
 constexpr int N_TILE_CFGS = 3;
 
 constexpr int LOSS_BLOCKS = 4096;   // blocks of the reduction kernels of the losses
