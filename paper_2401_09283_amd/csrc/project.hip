@@ -8,10 +8,14 @@
 // coordinates [-1, n] per axis) is split into N = ceil(length / h) equal steps, h half the
 // smallest voxel pitch, and the integral is the midpoint sum (mm x volume units).
 //
-// One thread per detector pixel, a workgroup per 16 x 16 pixel patch and view (neighbouring
-// rays share cache lines of the volume). The ray set-up (inverse, clipping, entry point) is
+// One thread per detector pixel, a workgroup per 4 columns x 64 rows of one view: a wave
+// takes 64 rows of one column, whose rays cross the same (x, y) columns of the volume at
+// nearby z, so each tap load of the wave touches one or two cache lines of the z-fastest
+// volume. The ray set-up (inverse, clipping, entry point) is
 // FP64; the march is FP32 from the entry point, so sample positions carry no cancellation
-// against the distant source.
+// against the distant source. Per sample the two taps along each axis are clamped into the
+// grid and a tap outside it gets weight 0 (the zero extension), so the eight loads need no
+// branches; indices are 32-bit when the volume has fewer than 2^31 voxels.
 #include "gmc_internal.hpp"
 
 namespace gmc {
@@ -28,16 +32,31 @@ struct FpArgs {
     double step_mm;
 };
 
-__device__ __forceinline__ float voxel_at(const FpArgs& a, int i, int j, int k) {
-    if ((unsigned)i >= (unsigned)a.nx || (unsigned)j >= (unsigned)a.ny || (unsigned)k >= (unsigned)a.nz) return 0.0f;
-    const long long idx = ((long long)i * a.ny + j) * a.nz + k;
-    if (a.labels && a.labels[idx] != a.part) return 0.0f;
-    return a.vol[idx];
+// The two taps of one axis: clamped indices and weights, 0 for a tap outside [0, n).
+struct AxisTaps {
+    int i0, i1;
+    float w0, w1;
+};
+
+__device__ __forceinline__ AxisTaps axis_taps(int i, float frac, int n) {
+    AxisTaps t;
+    t.i0 = min(max(i, 0), n - 1);
+    t.i1 = min(max(i + 1, 0), n - 1);
+    t.w0 = ((unsigned)i < (unsigned)n) ? 1.0f - frac : 0.0f;
+    t.w1 = ((unsigned)(i + 1) < (unsigned)n) ? frac : 0.0f;
+    return t;
 }
 
+template <typename Idx, bool LABELS>
+__device__ __forceinline__ float tap(const FpArgs& a, Idx idx) {
+    const float x = a.vol[idx];
+    return LABELS ? (a.labels[idx] == a.part ? x : 0.0f) : x;
+}
+
+template <typename Idx, bool LABELS>
 __global__ void __launch_bounds__(256) k_forward_project(FpArgs a) {
-    const int c = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int r = blockIdx.y * 16 + (threadIdx.x >> 4);
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int r = blockIdx.y * 64 + (threadIdx.x & 63);
     const int v = blockIdx.z;
     if (c >= a.W || r >= a.H) return;
     const double* P = a.Phat + 12 * (long long)v;
@@ -79,20 +98,22 @@ __global__ void __launch_bounds__(256) k_forward_project(FpArgs a) {
         const float qx = (float)(q0[0] + (t0 + 0.5 * dt) * dq[0]), qy = (float)(q0[1] + (t0 + 0.5 * dt) * dq[1]),
                     qz = (float)(q0[2] + (t0 + 0.5 * dt) * dq[2]);
         const float sx = (float)(dt * dq[0]), sy = (float)(dt * dq[1]), sz = (float)(dt * dq[2]);
+        const Idx sx_i = (Idx)a.ny * a.nz, sy_i = a.nz;
         for (long long s = 0; s < N; ++s) {
             const float fs = (float)s;
             const float px = fmaf(fs, sx, qx), py = fmaf(fs, sy, qy), pz = fmaf(fs, sz, qz);
             const float fx = floorf(px), fy = floorf(py), fz = floorf(pz);
-            const float ax = px - fx, ay = py - fy, az = pz - fz;
-            const int i = (int)fx, j = (int)fy, k = (int)fz;
-            const float v000 = voxel_at(a, i, j, k), v001 = voxel_at(a, i, j, k + 1);
-            const float v010 = voxel_at(a, i, j + 1, k), v011 = voxel_at(a, i, j + 1, k + 1);
-            const float v100 = voxel_at(a, i + 1, j, k), v101 = voxel_at(a, i + 1, j, k + 1);
-            const float v110 = voxel_at(a, i + 1, j + 1, k), v111 = voxel_at(a, i + 1, j + 1, k + 1);
-            const float z00 = fmaf(az, v001 - v000, v000), z01 = fmaf(az, v011 - v010, v010);
-            const float z10 = fmaf(az, v101 - v100, v100), z11 = fmaf(az, v111 - v110, v110);
-            const float y0 = fmaf(ay, z01 - z00, z00), y1 = fmaf(ay, z11 - z10, z10);
-            sum += fmaf(ax, y1 - y0, y0);
+            const AxisTaps tx = axis_taps((int)fx, px - fx, a.nx);
+            const AxisTaps ty = axis_taps((int)fy, py - fy, a.ny);
+            const AxisTaps tz = axis_taps((int)fz, pz - fz, a.nz);
+            const Idx r00 = (Idx)tx.i0 * sx_i + (Idx)ty.i0 * sy_i, r01 = (Idx)tx.i0 * sx_i + (Idx)ty.i1 * sy_i;
+            const Idx r10 = (Idx)tx.i1 * sx_i + (Idx)ty.i0 * sy_i, r11 = (Idx)tx.i1 * sx_i + (Idx)ty.i1 * sy_i;
+            const float z00 = fmaf(tz.w0, tap<Idx, LABELS>(a, r00 + tz.i0), tz.w1 * tap<Idx, LABELS>(a, r00 + tz.i1));
+            const float z01 = fmaf(tz.w0, tap<Idx, LABELS>(a, r01 + tz.i0), tz.w1 * tap<Idx, LABELS>(a, r01 + tz.i1));
+            const float z10 = fmaf(tz.w0, tap<Idx, LABELS>(a, r10 + tz.i0), tz.w1 * tap<Idx, LABELS>(a, r10 + tz.i1));
+            const float z11 = fmaf(tz.w0, tap<Idx, LABELS>(a, r11 + tz.i0), tz.w1 * tap<Idx, LABELS>(a, r11 + tz.i1));
+            const float y0 = fmaf(ty.w0, z00, ty.w1 * z01), y1 = fmaf(ty.w0, z10, ty.w1 * z11);
+            sum += fmaf(tx.w0, y0, tx.w1 * y1);
         }
         sum *= (float)(len / (double)N);
     }
@@ -123,8 +144,16 @@ hipError_t launch_forward_project(const gmc_plan* p, const float* vol, const uin
     a.oy = p->g.origin_mm[1];
     a.oz = p->g.origin_mm[2];
     a.step_mm = 0.5 * fmin(a.vx, fmin(a.vy, a.vz));
-    const dim3 grid((unsigned)((a.W + 15) / 16), (unsigned)((a.H + 15) / 16), (unsigned)p->g.n_views);
-    k_forward_project<<<grid, 256, 0, s>>>(a);
+    const dim3 grid((unsigned)((a.W + 3) / 4), (unsigned)((a.H + 63) / 64), (unsigned)p->g.n_views);
+    const bool small = (long long)a.nx * a.ny * a.nz < (1LL << 31);
+    if (small && labels)
+        k_forward_project<int, true><<<grid, 256, 0, s>>>(a);
+    else if (small)
+        k_forward_project<int, false><<<grid, 256, 0, s>>>(a);
+    else if (labels)
+        k_forward_project<long long, true><<<grid, 256, 0, s>>>(a);
+    else
+        k_forward_project<long long, false><<<grid, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
