@@ -38,7 +38,10 @@ PEAK_LDS_TBPS = 128 * 256 * 2.4e9 / 1e12   # 128 B/clk/CU (CDNA3 figure) x 256 C
 # elementwise kernel of known size (--copy-calib-mib). Valid only for the kernel source the
 # counters were taken on: the file records its hash, and traffic is null when it differs.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bp_vjp_head256_traffic.md")
-KERNEL_SOURCES = ("paper_2401_09283_amd/csrc/backproject.hip", "paper_2401_09283_amd/csrc/gmc_internal.hpp")
+# the code that decides the recorded counters: the kernel, its descriptors (tiles, modes) and
+# the plan (tile configuration, view chunks)
+KERNEL_SOURCES = ("paper_2401_09283_amd/csrc/backproject.hip", "paper_2401_09283_amd/csrc/gmc_internal.hpp",
+                  "paper_2401_09283_amd/csrc/compose.hip", "paper_2401_09283_amd/csrc/api.hip")
 
 
 def percentile(xs, q):

@@ -69,13 +69,13 @@ def test_view_chunks_follow_the_brick_count():
     # never more chunks than views
     assert gmc.Plan(_geom(n_views=2)).info()["view_chunks"] == (2, 2)
     assert gmc.Plan(_geom(n_views=1)).info()["view_chunks"] == (1, 1)
-    # a volume that fills the GPU by its bricks alone: 4 chunks in both passes
+    # a volume that fills the GPU by its bricks alone: 4 forward chunks, 16 VJP chunks
     g = gmc.make_geometry(16, 64, 64, (256, 256, 256), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
     info = gmc.Plan(g).info()
-    assert info["n_bricks"] == 16 * 16 * 32 and info["view_chunks"] == (4, 4)
+    assert info["n_bricks"] == 16 * 16 * 32 and info["view_chunks"] == (4, 16)
     # the forward's partial volumes stay within 4 GiB
     g = gmc.make_geometry(16, 64, 64, (1024, 1024, 1024), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
-    assert gmc.Plan(g).info()["view_chunks"] == (2, 4)
+    assert gmc.Plan(g).info()["view_chunks"] == (2, 16)
 
 
 def test_nominal_geometry_picks_the_tile():
