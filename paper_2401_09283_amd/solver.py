@@ -169,6 +169,29 @@ class MotionSolver:
         else:
             raise ValueError("unknown optimizer %r" % c.optimizer)
 
+    # ---------------------------------------------------------------- checkpoint / resume
+    def state_dict(self) -> dict:
+        """Everything an interrupted solve needs to continue bitwise identically: the
+        coefficients, Adam moments, iteration count, TV weight and Eq. 6 step (host copies;
+        save with torch.save, load with torch.load(..., weights_only=True))."""
+        return dict(coeffs=self.coeffs.cpu(), m=self.m.cpu(), v=self.v.cpu(), it=int(self.it),
+                    lam=None if self.lam is None else float(self.lam),
+                    gd_s0=None if self.gd_s0 is None else float(self.gd_s0),
+                    n_nodes=int(self.cfg.n_nodes), motion=self.cfg.motion, n_views=int(self.n_views))
+
+    def load_state_dict(self, st: dict) -> None:
+        if (int(st["n_nodes"]) != self.cfg.n_nodes or st["motion"] != self.cfg.motion
+                or int(st["n_views"]) != self.n_views):
+            raise ValueError("checkpoint of another problem (nodes, motion model or views differ)")
+        for name in ("coeffs", "m", "v"):
+            src = st[name]
+            if tuple(src.shape) != tuple(self.coeffs.shape):
+                raise ValueError("checkpoint tensor %s has shape %s" % (name, tuple(src.shape)))
+            getattr(self, name).copy_(src.to(device=self.coeffs.device, dtype=torch.float64))
+        self.it = int(st["it"])
+        self.lam = st["lam"]
+        self.gd_s0 = st["gd_s0"]
+
     def run(self, n_iter=None, record_loss=False):
         """n_iter iterations; the loss of every iteration is kept on the device and read once."""
         n_iter = self.cfg.n_iter if n_iter is None else n_iter
