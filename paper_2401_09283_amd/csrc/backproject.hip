@@ -5,15 +5,18 @@
 // tile in LDS (the filtered projection, with a one-pixel halo for the central differences of
 // Sec. II-B.2, which are formed from the tile's taps on the fly), then every thread walks its
 // column: homogeneous position by FMA from the column base, one reciprocal per column and a
-// Newton step per sample, bilinear taps from LDS. The forward pass accumulates its BZ voxels
-// in registers over all views and writes them once (z fastest). The VJP keeps the seed of its
-// BZ voxels in registers, sums the per-sample row coefficients of Eq. 4 (6 running sums per
-// thread, since x and y are constant along a column), reduces them over the workgroup with
+// Newton step per sample, bilinear taps from LDS. A workgroup takes one item: a brick and a
+// contiguous chunk of its views. The forward pass accumulates its BZ voxels in registers over
+// the chunk's views and writes them once (z fastest; chunks after the first into partial
+// volumes that are summed afterwards in chunk order). The VJP keeps the seed of its BZ voxels
+// in registers, sums the per-sample row coefficients of Eq. 4 (6 running sums per thread,
+// since x and y are constant along a column), reduces them over the workgroup with
 // cross-lane permutes at the end of each view and writes one 12-entry partial per
 // (view, brick); k_reduce_chain finishes the sum.
 //
-// Workgroups are mapped to bricks so that each XCD (workgroup id mod 8) takes a contiguous
-// range of z-slabs: its L2 then holds only the detector rows those slabs project to.
+// Items are numbered chunk-major and each XCD (workgroup id mod 8) takes a contiguous range
+// of them: the workgroups resident on an XCD are neighbouring bricks over the same views,
+// and every XCD gets a share of the whole volume (equal work).
 #include "gmc_internal.hpp"
 
 namespace gmc {
