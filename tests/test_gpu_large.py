@@ -1,6 +1,7 @@
 """The 512^3 x 496-view scan (0.5 mm voxels, 976x976 detector): parity at sampled voxels and
 with a sparse seed, sample positions recomputed per brick (never stored), and the peak HBM
-footprint of a full forward + VJP."""
+footprint of a full forward + VJP. Also the largest serving size, 384^3 x 496 views at
+0.667 mm on the 620x480 detector, at sampled voxels and with a sparse seed."""
 import numpy as np
 import pytest
 import torch
@@ -49,3 +50,28 @@ def test_large_scan_parity_and_footprint(c3):
     assert np.all(eg <= GRAD_TOL)
     # storing (u/w, v/w, w) per voxel and view would take 512^3 * 496 * 12 B = 799 GB
     assert peak < 10.0
+
+
+def test_serving_size_384_parity():
+    c = case("serve384")
+    bp = Backprojector.from_case(c)
+    proj = torch.from_numpy(c.proj).to(DEV)
+    theta = torch.from_numpy(c.theta_true).to(DEV)
+    vol = bp.forward(proj, theta)
+    bp.check()
+    idx = sample_voxels(c.grid, 8)
+    Phat, dPhat = oracle.compose(c.theta_true, c.P)
+    geo = oracle.geom_from(c.scan, c.grid, "fdk", "paper")
+    ref = oracle.backproject_voxels(geo, c.proj, Phat, idx)
+    ev = float(np.max(np.abs(vol.cpu().numpy().ravel()[idx] - ref)) / np.max(np.abs(ref)))
+    rng = np.random.default_rng(98)
+    sidx = np.unique(rng.integers(0, c.grid.n_voxels, 300))
+    sval = rng.standard_normal(len(sidx)).astype(np.float32)
+    seed = torch.zeros(c.grid.n_voxels, dtype=torch.float32, device=DEV)
+    seed[torch.from_numpy(sidx).to(DEV)] = torch.from_numpy(sval).to(DEV)
+    g = bp.vjp(proj, theta, seed.reshape(c.grid.shape))
+    G = oracle.vjp_sparse(geo, c.proj, Phat, sidx, sval.astype(np.float64))
+    eg = grad_err(g.cpu().numpy(), oracle.chain(G, dPhat))
+    print("[384^3] volume err %.2e gradient err %s" % (ev, np.array2string(eg, precision=2)), flush=True)
+    assert ev <= VOL_TOL
+    assert np.all(eg <= GRAD_TOL)
