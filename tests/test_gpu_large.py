@@ -1,7 +1,8 @@
 """The 512^3 x 496-view scan (0.5 mm voxels, 976x976 detector): parity at sampled voxels and
 with a sparse seed, sample positions recomputed per brick (never stored), and the peak HBM
-footprint of a full forward + VJP. Also the largest serving size, 384^3 x 496 views at
-0.667 mm on the 620x480 detector, at sampled voxels and with a sparse seed."""
+footprint of a full forward + VJP. Also the largest serving size (384^3 x 496 views at
+0.667 mm on the 620x480 detector) and the paper's shape, at sampled voxels and with a sparse
+seed."""
 import numpy as np
 import pytest
 import torch
@@ -52,8 +53,11 @@ def test_large_scan_parity_and_footprint(c3):
     assert peak < 10.0
 
 
-def test_serving_size_384_parity():
-    c = case("serve384")
+@pytest.mark.parametrize("name", ["serve384", "paper128"])
+def test_sampled_parity_at_full_size(name):
+    """384^3 x 496 views (largest serving size) and the paper's shape (128^3 @ 2 mm, 360 views,
+    700 x 500 @ 0.64 mm, Akima motion; the 128 x 64 tile)."""
+    c = case(name)
     bp = Backprojector.from_case(c)
     proj = torch.from_numpy(c.proj).to(DEV)
     theta = torch.from_numpy(c.theta_true).to(DEV)
@@ -72,6 +76,6 @@ def test_serving_size_384_parity():
     g = bp.vjp(proj, theta, seed.reshape(c.grid.shape))
     G = oracle.vjp_sparse(geo, c.proj, Phat, sidx, sval.astype(np.float64))
     eg = grad_err(g.cpu().numpy(), oracle.chain(G, dPhat))
-    print("[384^3] volume err %.2e gradient err %s" % (ev, np.array2string(eg, precision=2)), flush=True)
+    print("[%s] volume err %.2e gradient err %s" % (name, ev, np.array2string(eg, precision=2)), flush=True)
     assert ev <= VOL_TOL
     assert np.all(eg <= GRAD_TOL)
