@@ -98,7 +98,11 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--channels", default="8,16,32,64")
+    ap.add_argument("--no-find", dest="find", action="store_false",
+                    help="keep the convolution library's default algorithms (no MIOpen find step)")
     args = ap.parse_args(argv)
+    # MIOpen times its convolution algorithms for each shape once (during the warm-up)
+    torch.backends.cudnn.benchmark = args.find
     cfg = CONFIGS[args.config]
     case = make_case(args.config)
     bp = Backprojector.from_case(case)
@@ -122,7 +126,7 @@ def main(argv=None):
     fwd = sum(e["f0"].elapsed_time(e["f1"]) for e in rec) / args.iters
     mid = sum(e["f1"].elapsed_time(e["v0"]) for e in rec) / args.iters
     vjp = sum(e["v0"].elapsed_time(e["v1"]) for e in rec) / args.iters
-    print(json.dumps(dict(config=args.config, channels=ch, ms_per_iter=ms, bp_forward_ms=fwd, unet_fwd_bwd_ms=mid,
+    print(json.dumps(dict(config=args.config, channels=ch, find=args.find, ms_per_iter=ms, bp_forward_ms=fwd, unet_fwd_bwd_ms=mid,
                           bp_vjp_ms=vjp, s_per_100_iters=ms / 10.0)), flush=True)
 
 
