@@ -80,6 +80,30 @@ class Server:
         self.used = 0
         self.ticks = 0
         self.batch_sizes = []
+        self._cancelled = set()
+
+    def cancel(self, rid: int) -> None:
+        """Cancel request rid (callable from another thread or from the executor): it leaves the
+        queue or its slot at the next tick, its memory is released, status 'cancelled'."""
+        self._cancelled.add(rid)
+
+    def _apply_cancellations(self, pending, waiting, active, t):
+        if not self._cancelled:
+            return pending, waiting, active
+        hit = set(self._cancelled)
+
+        def drop(lst, release):
+            keep = []
+            for r in lst:
+                if r.rid in hit:
+                    r.status, r.error, r.t_done = "cancelled", "cancelled", t
+                    if release:
+                        self._release(r)
+                else:
+                    keep.append(r)
+            return keep
+
+        return drop(pending, False), drop(waiting, False), drop(active, True)
 
     def run(self, requests):
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -90,6 +114,7 @@ class Server:
         self._now = now
         while pending or waiting or active:
             t = now()
+            pending, waiting, active = self._apply_cancellations(pending, waiting, active, t)
             while pending and pending[0].arrival <= t:
                 waiting.append(pending.pop(0))
             # FIFO admission by slots and HBM footprint

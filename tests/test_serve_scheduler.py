@@ -190,3 +190,29 @@ def test_srpt_with_a_waiting_cap_serves_old_requests_first():
     Server(ex2, 1000, 8, clock=clk2, sleep=clk2.sleep, policy="srpt", tick_work=2.0).run(
         [Request(0, 0.0, 3, {"bytes": 10, "work": 10.0}), Request(1, 0.05, 6, {"bytes": 10, "work": 1.0})])
     assert [e[1] for e in ex2.log if e[0] == "step"] == [(0,)] + [(1,)] * 6 + [(0,), (0,)]
+
+
+def test_cancellation_frees_the_slot_and_the_memory():
+    clk = FakeClock()
+
+    class CancellingExecutor(FakeExecutor):
+        server = None
+
+        def step(self, reqs):
+            super().step(reqs)
+            if self.steps == 2:
+                self.server.cancel(0)   # the long request, while it is active
+                self.server.cancel(3)   # a request that has not arrived yet
+
+    ex = CancellingExecutor(clk, tick=0.1)
+    srv = Server(ex, hbm_budget_bytes=100, max_active=2, clock=clk, sleep=clk.sleep, policy="all")
+    ex.server = srv
+    reqs = srv.run(make([(0, 0.0, 50, 60), (1, 0.0, 2, 40), (2, 0.05, 2, 60), (3, 5.0, 1, 10)]))
+    st = {r.rid: r.status for r in reqs}
+    assert st == {0: "cancelled", 1: "done", 2: "done", 3: "cancelled"}
+    # 2 (60 B) could only be admitted once 0 (60 B) was cancelled and released
+    rel0 = next(i for i, e in enumerate(ex.log) if e[0] == "release" and e[1] == 0)
+    adm2 = next(i for i, e in enumerate(ex.log) if e[0] == "admit" and e[1] == 2)
+    assert adm2 > rel0
+    assert srv.used == 0 and not ex.resident
+    assert sum(1 for e in ex.log if e[0] == "step" and 0 in e[1]) == 2
