@@ -126,12 +126,13 @@ def test_tv_of_constant_and_of_a_step():
     assert T == pytest.approx(36.0, rel=1e-9)
 
 
-@pytest.mark.parametrize("which", ["sumsq", "entropy", "tv"])
+@pytest.mark.parametrize("which", ["sumsq", "entropy", "tv", "entropy_tv"])
 def test_loss_seeds_match_finite_differences(which):
     rng = np.random.default_rng(12)
     I = 0.025 + 0.015 * rng.standard_normal((7, 6, 5))
-    f = {"sumsq": losses.sumsq_grad, "entropy": losses.entropy, "tv": lambda v: losses.tv(v, 1e-3)}[which]
-    L, g = f(I)
+    f = {"sumsq": losses.sumsq_grad, "entropy": losses.entropy, "tv": lambda v: losses.tv(v, 1e-3),
+         "entropy_tv": lambda v: losses.entropy_tv(v, 0.3, eps=1e-3)}[which]
+    L, g = f(I)[:2]
     for q in rng.choice(I.size, 25, replace=False):
         e = np.zeros(I.size)
         e[q] = 1e-7
