@@ -80,7 +80,8 @@ typedef struct gmc_plan gmc_plan;
 /* Create a plan for one geometry. P_nominal (HOST pointer, [n_views][3][4] float64, or
  * NULL) is the static scan; it sizes the on-chip detector tiles (a pair whose tile
  * exceeds them at run time is sampled from global memory instead, with identical
- * results). Host-only; allocates host memory only. */
+ * results). Host-only; allocates host memory only. GMC_E_UNSUPPORTED beyond 2^26 bricks of
+ * 16 x 16 x 8 voxels (about 1.4e11 voxels) or 2^33 (brick, view) pairs. */
 gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_plan** out);
 gmc_status gmc_plan_destroy(gmc_plan* plan);
 /* Bytes of device workspace every call on this plan needs (256-byte aligned pointer). */

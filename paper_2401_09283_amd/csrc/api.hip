@@ -202,7 +202,8 @@ gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_p
     p->nby = (g->ny + BXY - 1) / BXY;
     p->nbz = (g->nz + p->bz - 1) / p->bz;
     const long long nb = (long long)p->nbx * p->nby * p->nbz;
-    if (nb > (1LL << 28) || nb * g->n_views > (1LL << 33)) {
+    // work items (brick, view chunk) are numbered in 32 bits: at most 2^26 bricks x 16 chunks
+    if (nb > (1LL << 26) || nb * g->n_views > (1LL << 33)) {
         delete p;
         return fail(GMC_E_UNSUPPORTED, "too many (brick, view) pairs");
     }
@@ -487,6 +488,9 @@ gmc_status gmc_launch_batch(const gmc_work* items, int32_t n_items, void* hip_st
                 it.plan->g.grad_mode != lead.plan->g.grad_mode)
                 continue;
             BpArgs ba = bp_args(it.plan, it.proj, carve(it.plan, it.workspace), it.phase == 1);
+            // the items of one launch are numbered in 32 bits: a plan that would overflow them
+            // waits for the next launch
+            if (tab.n > 0 && (long long)tab.total + (long long)it.plan->n_bricks * ba.vsplit > (1LL << 30)) continue;
             ba.vol = it.vol;
             ba.gvol = it.grad_vol;
             tab.item[tab.n] = ba;

@@ -49,6 +49,17 @@ def test_invalid_geometry_is_rejected(bad):
     assert e.value.status == -1
 
 
+@pytest.mark.parametrize("big", [dict(shape=(1 << 14, 1 << 14, 1 << 13)),              # > 2^40 voxels
+                                 dict(shape=(1 << 13, 1 << 13, 1 << 12)),              # 2^27 bricks
+                                 dict(shape=(1 << 12, 1 << 12, 1 << 10), n_views=1 << 16)])  # 2^34 pairs
+def test_oversized_geometry_is_unsupported(big):
+    """Work items are numbered in 32 bits: plans beyond 2^26 bricks or 2^33 (brick, view) pairs
+    are refused before anything is sized."""
+    with pytest.raises(gmc.GmcError) as e:
+        gmc.Plan(_geom(**big))
+    assert e.value.status == -5
+
+
 def test_plan_bricks_and_workspace():
     p = gmc.Plan(_geom())
     info = p.info()
