@@ -50,6 +50,25 @@ def test_forward_projection_matches_oracle_tiny():
     assert e <= VOL_TOL
 
 
+@pytest.mark.parametrize("nz", [1, 2, 3])
+def test_forward_projection_of_thin_volumes(nz):
+    """One, two and three slices: every z tap pair is clamped at the grid's top or bottom (nz = 1
+    takes the single-load path, nz >= 2 the paired loads); ragged x and y."""
+    c = case("tiny")
+    shape = (21, 18, nz)
+    origin = tuple(-(n - 1) / 2.0 for n in shape)
+    bp = Backprojector(c.scan.n_views, c.scan.det_w, c.scan.det_h, shape, (1.0, 1.0, 1.0), origin, c.P)
+    vol = np.random.default_rng(5 + nz).uniform(0.1, 1.0, shape).astype(np.float32)
+    out = torch.empty(bp.plan.proj_shape, dtype=torch.float32, device=DEV)
+    gmc.gmc_forward_project(bp.plan, _t(vol, torch.float32), bp.P, _t(c.theta_true, torch.float64), out, bp.workspace)
+    Phat, _ = oracle.compose(c.theta_true, c.P)
+    g = oracle.geom(c.scan.n_views, c.scan.det_w, c.scan.det_h, shape, (1.0, 1.0, 1.0), origin)
+    ref = oracle.forward_project(g, vol, Phat)
+    e = _err(out.cpu().numpy(), ref)
+    print("[projector thin nz=%d] err %.2e" % (nz, e), flush=True)
+    assert np.max(np.abs(ref)) > 0 and e <= VOL_TOL
+
+
 def test_forward_projection_of_moving_parts():
     c = case("tiny")
     bp = Backprojector.from_case(c)
