@@ -149,7 +149,8 @@ gmc_status gmc_loss_entropy_tv(const gmc_plan* plan, const float* vol, double la
  * through pixel (c, r), of the trilinear interpolant of vol (float32 [nx][ny][nz], values at the
  * voxel centres, zero outside the grid), by the midpoint rule over equal steps of at most half
  * the smallest voxel pitch (units: mm x volume units). Device pointers; the workspace's matrix
- * area is overwritten. */
+ * area is overwritten. GMC_E_UNSUPPORTED for an axis longer than 2^22 voxels or rays of more than
+ * 2^24 steps. */
 gmc_status gmc_forward_project(const gmc_plan* plan, const float* vol, const double* P, const double* theta,
                                float* proj_out, void* workspace, void* hip_stream);
 /* Several independently moving rigid parts: voxel p belongs to part labels[p] (uint8 [nx][ny][nz],

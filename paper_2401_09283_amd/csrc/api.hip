@@ -350,6 +350,15 @@ gmc_status gmc_forward_project_parts(const gmc_plan* plan, const float* vol, con
     if (!vol || !P || !theta || !proj_out) return fail(GMC_E_INVALID, "NULL array argument");
     if (n_parts < 1 || n_parts > 255 || (n_parts > 1 && !labels))
         return fail(GMC_E_INVALID, "need 1 <= n_parts <= 255 and labels when n_parts > 1");
+    // the march counts samples and voxel coordinates in FP32 / 32-bit integers: every ray has
+    // fewer than 2^24 samples (the support's diagonal over half the smallest voxel pitch)
+    {
+        const gmc_geometry& g = plan->g;
+        const double ex = (g.nx + 1) * g.voxel_mm[0], ey = (g.ny + 1) * g.voxel_mm[1], ez = (g.nz + 1) * g.voxel_mm[2];
+        const double h = 0.5 * std::min({g.voxel_mm[0], g.voxel_mm[1], g.voxel_mm[2]});
+        if (std::max({g.nx, g.ny, g.nz}) > (1 << 22) || sqrt(ex * ex + ey * ey + ez * ez) / h + 2.0 > 16777216.0)
+            return fail(GMC_E_UNSUPPORTED, "forward projection: more than 2^24 samples per ray or an axis longer than 2^22 voxels");
+    }
     const WS w = carve(plan, workspace);
     const hipStream_t s = (hipStream_t)hip_stream;
     const long long nv = plan->g.n_views;

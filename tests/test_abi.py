@@ -99,6 +99,19 @@ def test_nominal_geometry_picks_the_tile():
         assert gmc.Plan(g, projection_matrices(cfg.scan)).info()["tile_pitch"] == pitch
 
 
+@pytest.mark.parametrize("geo", [dict(shape=(1 << 23, 2, 2)),                                  # axis > 2^22
+                                 dict(shape=(4096, 4096, 64), voxel_mm=(1.0, 1.0, 1e-4))])   # > 2^24 steps
+def test_forward_projection_refuses_rays_it_cannot_count(geo):
+    """The projector's march counts samples in FP32: geometries beyond 2^24 steps per ray (or an
+    axis beyond 2^22 voxels) are refused before anything is launched (the pointers here are
+    never dereferenced)."""
+    L = _lib.lib()
+    p = gmc.Plan(_geom(**geo))
+    fake = ctypes.c_void_p(256)
+    assert L.gmc_forward_project(p.handle, fake, fake, fake, fake, fake, None) == -5
+    assert b"2^24" in L.gmc_last_error()
+
+
 def test_null_workspace_and_arguments_are_rejected_without_launching():
     L = _lib.lib()
     p = gmc.Plan(_geom())
