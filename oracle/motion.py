@@ -6,8 +6,10 @@
   N_n coefficients and knots t_m = (m - 1) h, h = (N_p - 1)/(N_n - 3), so
   that exactly four basis functions cover every view 0..N_p-1.
   Coefficients are held in (mm, mm, mm, deg, deg, deg); theta in (mm, rad).
-* Gradient descent with exponential step decay is Eq. 6; the solver used
-  here is Adam (Kingma & Ba), which the paper's discussion suggests.
+* Gradient descent with exponential step decay is Eq. 6 (Sec. II-C): the
+  estimate moves against the gradient by s_n = s0 * t^n at iteration n,
+  counted from 0; the workloads' solver is Adam (Kingma & Ba), which the
+  paper's discussion suggests.
 * Reprojection error (Sec. IV): mean detector distance (mm) between points
   projected with the estimated and the true geometry.
 * The paper's own motion model (Sec. II-B.1) is an Akima spline per rigid parameter
@@ -69,6 +71,16 @@ def adam_step(x, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mh = m / (1.0 - beta1 ** t)
     vh = v / (1.0 - beta2 ** t)
     return x - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def gd_step_size(n, s0, decay):
+    """Step size of Eq. 6 at iteration n (0-based): s0 * decay^n (Sec. II-C)."""
+    return float(s0) * float(decay) ** int(n)
+
+
+def gd_step(x, g, n, s0, decay):
+    """One update of Eq. 6: x^(n+1) = x^(n) - s^(n) g, with s^(n) = s0 decay^n."""
+    return np.asarray(x, dtype=np.float64) - gd_step_size(n, s0, decay) * np.asarray(g, dtype=np.float64)
 
 
 # ------------------------------------------------------------------------------ Akima spline
