@@ -19,9 +19,10 @@ GRAD = {"paper": 0, "exact": 1}
 FLAG_FORCE_GLOBAL = 1
 FLAG_FORCE_EDGE = 2
 WORK_PREPARED = 1
+NOALLOC_SCRATCH_BYTES = 64 << 20   # GMC_NOALLOC_SCRATCH_BYTES
 
 EXPORTS = ["gmc_plan_create", "gmc_plan_destroy", "gmc_workspace_bytes", "gmc_plan_info", "gmc_compose",
-           "gmc_backproject", "gmc_backproject_vjp", "gmc_prepare", "gmc_bp_forward", "gmc_bp_vjp",
+           "gmc_backproject", "gmc_backproject_vjp", "gmc_backproject_vjp_noalloc", "gmc_prepare", "gmc_bp_forward", "gmc_bp_vjp",
            "gmc_bp_vjp_finish", "gmc_loss_sumsq_grad", "gmc_loss_entropy_tv",
            "gmc_bspline_theta", "gmc_bspline_grad", "gmc_akima_theta", "gmc_akima_grad", "gmc_forward_project", "gmc_forward_project_parts", "gmc_adam_step", "gmc_gd_step", "gmc_debug_project",
            "gmc_launch_batch", "gmc_check", "gmc_status_string", "gmc_last_error"]
@@ -67,6 +68,7 @@ def lib():
         "gmc_compose": ([vp, vp, vp, vp, vp, vp], i32),
         "gmc_backproject": ([vp, vp, vp, vp, vp, vp, vp], i32),
         "gmc_backproject_vjp": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
+        "gmc_backproject_vjp_noalloc": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i32),
         "gmc_prepare": ([vp, vp, vp, i32, vp, vp], i32),
         "gmc_bp_forward": ([vp, vp, vp, vp, vp], i32),
         "gmc_bp_vjp": ([vp, vp, vp, vp, vp], i32),

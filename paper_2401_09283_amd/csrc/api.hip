@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <utility>
 #include <new>
 #include <string>
@@ -185,6 +186,40 @@ gmc_status prepare(const gmc_plan* p, const double* P, const double* theta, cons
     return GMC_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free VJP
+//
+// gmc_backproject_vjp_noalloc carves its workspace from this file-scope device array instead of
+// a caller-owned buffer. In host code the name `scratch` is a host-side stand-in, not a device
+// address: the address comes from hipGetSymbolAddress, once per device with that device current,
+// and only that pointer reaches kernels. Every GPU the library runs on holds its own copy of the
+// array until the process ends.
+static __device__ __align__(256) unsigned char scratch[GMC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+gmc_status scratch_of_current_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(GMC_E_UNSUPPORTED, "device %d: the allocation-free entry point serves devices 0..%d", dev,
+                    NOALLOC_MAX_DEVICES - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(GMC_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GMC_OK;
+}
+
+__global__ void k_copy_int(const int* src, int32_t* dst) { *dst = *src; }
+
 }  // namespace
 
 extern "C" {
@@ -335,6 +370,37 @@ gmc_status gmc_backproject_vjp(const gmc_plan* plan, const float* proj, const do
     if ((st = gmc_prepare(plan, P, theta, 1, workspace, hip_stream)) != GMC_OK) return st;
     if ((st = gmc_bp_vjp(plan, proj, grad_vol, workspace, hip_stream)) != GMC_OK) return st;
     return gmc_bp_vjp_finish(plan, grad_theta, grad_P, workspace, hip_stream);
+}
+
+gmc_status gmc_backproject_vjp_noalloc(const gmc_plan* plan, const float* proj, const double* P,
+                                       const double* theta, const float* grad_vol, double* grad_theta,
+                                       double* grad_P, int32_t* geometry_flag, void* hip_stream) {
+    if (!plan) return fail(GMC_E_INVALID, "plan is NULL");
+    if (!proj || !P || !theta || !grad_vol || !grad_theta) return fail(GMC_E_INVALID, "NULL array argument");
+    // the VJP touches the workspace up to the status word (matrices, descriptors, partials, G)
+    const size_t need = plan->off_loss;
+    if (need > (size_t)GMC_NOALLOC_SCRATCH_BYTES)
+        return fail(GMC_E_UNSUPPORTED,
+                    "allocation-free VJP: this plan needs %zu bytes of scratch (%d bricks x %d views), the static "
+                    "buffer holds %zu; use gmc_backproject_vjp with a caller workspace",
+                    need, plan->n_bricks, plan->g.n_views, (size_t)GMC_NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    gmc_status st = scratch_of_current_device(&ws);
+    if (st != GMC_OK) return st;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    const WS w = carve(plan, ws);
+    if ((st = prepare(plan, P, theta, w, true, s)) != GMC_OK) return st;
+    BpArgs a = bp_args(plan, proj, w, true);
+    a.gvol = grad_vol;
+    hipError_t e = launch_bp(plan, a, true, s);
+    if (e != hipSuccess) return hip_fail(e, "vjp");
+    e = launch_reduce_chain(plan, w.part, w.dPhat, w.G, grad_theta, grad_P, s);
+    if (e != hipSuccess) return hip_fail(e, "reduce/chain");
+    if (geometry_flag) {
+        hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(1), 0, s, (const int*)w.status, geometry_flag);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "geometry flag");
+    }
+    return GMC_OK;
 }
 
 gmc_status gmc_forward_project(const gmc_plan* plan, const float* vol, const double* P, const double* theta,

@@ -133,6 +133,19 @@ def gmc_backproject_vjp(plan: Plan, proj, P, theta, grad_vol, grad_theta, grad_P
                                     _stream(stream)), "gmc_backproject_vjp")
 
 
+def gmc_backproject_vjp_noalloc(plan: Plan, proj, P, theta, grad_vol, grad_theta, grad_P=None, geometry_flag=None,
+                                stream=None):
+    n = plan.geometry.n_views
+    check(lib().gmc_backproject_vjp_noalloc(plan.handle, _ptr(proj, torch.float32, plan.proj_shape, "proj"),
+                                            _ptr(P, torch.float64, (n, 3, 4), "P"),
+                                            _ptr(theta, torch.float64, (n, 6), "theta"),
+                                            _ptr(grad_vol, torch.float32, plan.vol_shape, "grad_vol"),
+                                            _ptr(grad_theta, torch.float64, (n, 6), "grad_theta"),
+                                            _ptr(grad_P, torch.float64, (n, 3, 4), "grad_P", True),
+                                            _ptr(geometry_flag, torch.int32, (1,), "geometry_flag", True),
+                                            _stream(stream)), "gmc_backproject_vjp_noalloc")
+
+
 def gmc_prepare(plan: Plan, P, theta, with_deriv, workspace, stream=None):
     n = plan.geometry.n_views
     check(lib().gmc_prepare(plan.handle, _ptr(P, torch.float64, (n, 3, 4), "P"),

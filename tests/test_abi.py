@@ -124,3 +124,20 @@ def test_null_workspace_and_arguments_are_rejected_without_launching():
     assert L.gmc_bspline_theta(10, 3, None, None, None) == -1
     assert L.gmc_adam_step(5, None, None, None, None, 0, 0.1, 0.9, 0.999, 1e-8, None) == -1
     assert b"t >= 1" in L.gmc_last_error()
+
+
+def test_allocation_free_vjp_refuses_plans_beyond_its_static_buffer():
+    """The 256^3 x 496-view plan needs ~0.5 GB of VJP scratch: refused before any launch or device
+    query (the pointers are never touched, so host stand-ins suffice)."""
+    g = gmc.make_geometry(496, 620, 480, (256, 256, 256), (1.0, 1.0, 1.0), (-127.5, -127.5, -127.5))
+    plan = gmc.Plan(g)
+    dummy = ctypes.c_void_p(256)
+    st = _lib.lib().gmc_backproject_vjp_noalloc(plan.handle, dummy, dummy, dummy, dummy, dummy, None, None, None)
+    assert st == -5
+    msg = _lib.lib().gmc_last_error().decode()
+    assert "static" in msg and "gmc_backproject_vjp" in msg
+    # a plan that fits is not refused by size (it would then need a GPU): 128^3 x 248 views
+    small = gmc.Plan(gmc.make_geometry(248, 310, 240, (128, 128, 128), (2.0, 2.0, 2.0), (-127.0, -127.0, -127.0)))
+    assert 128 * 248 * 1024 < _lib.NOALLOC_SCRATCH_BYTES
+    st = _lib.lib().gmc_backproject_vjp_noalloc(small.handle, None, dummy, dummy, dummy, dummy, None, None, None)
+    assert st == -1   # NULL proj: an argument error, returned before the size check matters
