@@ -25,6 +25,7 @@ def c3():
 
 def test_large_scan_parity_and_footprint(c3):
     torch.cuda.reset_peak_memory_stats()
+    base = torch.cuda.memory_allocated()   # whatever earlier tests still hold is not this scan's
     bp = Backprojector.from_case(c3)
     proj = torch.from_numpy(c3.proj).to(DEV)
     theta = torch.from_numpy(c3.theta_true).to(DEV)
@@ -43,7 +44,7 @@ def test_large_scan_parity_and_footprint(c3):
     g = bp.vjp(proj, theta, seed.reshape(c3.grid.shape))
     G = oracle.vjp_sparse(geo, c3.proj, Phat, sidx, sval.astype(np.float64))
     eg = grad_err(g.cpu().numpy(), oracle.chain(G, dPhat))
-    peak = torch.cuda.max_memory_allocated() / 1e9
+    peak = (torch.cuda.max_memory_allocated() - base) / 1e9
     inputs = (c3.proj.nbytes + 2 * 4 * c3.grid.n_voxels) / 1e9
     print("[512^3] volume err %.2e gradient err %s peak HBM %.2f GB (inputs+volumes %.2f GB, workspace %.2f GB)"
           % (ev, np.array2string(eg, precision=2), peak, inputs, bp.plan.workspace_bytes / 1e9), flush=True)
