@@ -3,38 +3,47 @@
 Requests arrive over time (e.g. a Poisson stream). The server admits a waiting request as
 soon as an active slot is free and its HBM footprint (projections, volumes, optimiser state,
 workspace) fits the budget, keeps everything of an admitted request resident on the device,
-and advances all active requests together: every scheduler tick is one solver iteration
-(spline -> compose -> backprojection -> loss -> VJP -> chain -> Adam) for every active
-request, with ONE backprojection launch and ONE VJP launch over the voxel bricks of all of
-them (gmc_launch_batch). Requests of different volume and view counts share the launches;
-each request's arithmetic is the same as when it runs alone, so its result is bitwise
-identical. A request that finishes its iterations retires and frees its memory; the next
-tick admits new arrivals.
+and advances the active requests with scheduler ticks; a tick enqueues one solver iteration
+(spline -> compose -> backprojection -> loss -> VJP -> chain -> Adam) for each request the
+policy picks. A request that finishes its iterations retires and frees its memory; the next
+tick admits new arrivals. Each request's arithmetic is the same as when it runs alone, so
+its result is bitwise identical to a plain solve.
+
+Two executors:
+* streams (default): every admitted request has its own HIP stream and its iterations are
+  enqueued there, at most ``depth`` iterations ahead of the device, with no device-wide
+  synchronisation: the host only polls events. Requests on different streams overlap on
+  the GPU, so the phases of one request that leave the GPU partly idle (loss, set-up,
+  reduction, optimiser, launch gaps) run beside the backprojection of another.
+* batched: every tick is one backprojection launch and one VJP launch over the voxel bricks of
+  all ticked requests (gmc_launch_batch), in lockstep, with a device synchronisation per tick.
 
 Which active requests a tick advances is the policy: ``"all"`` advances every active request
-(processor sharing), ``"srpt"`` (the default) advances the requests with the least remaining work first
-(remaining iterations times the voxel-view updates of one iteration), adding requests to the
-tick until its work reaches ``tick_work`` updates (at least one request): small requests
-share launches and finish early, a large request runs alone once nothing smaller waits. With
-``max_wait`` set, requests that arrived more than ``max_wait`` seconds ago go first, oldest
-first, which bounds how long a large request can be overtaken.
-Results do not depend on the policy: every request's own iterations are the same.
+(processor sharing), ``"srpt"`` (the default) advances the requests with the least remaining
+work first (remaining iterations times the voxel-view updates of one iteration), adding
+requests to the tick until its work reaches ``tick_work`` updates (at least one request, and
+at least ``min_batch`` while that many are active): small requests finish early, a large
+request runs with at most a few others. With ``max_wait`` set, requests that arrived more
+than ``max_wait`` seconds ago go first, oldest first, which bounds how long a large request
+can be overtaken. Results do not depend on the policy or the executor.
 
 The scheduler is independent of the GPU: ``Server`` drives an executor with four calls
-(footprint, admit, step, release) and an optional fifth (work: updates per iteration), so its
-admission, policy and retirement logic is tested on the CPU with a fake executor and a fake
+(footprint, admit, step, release), an optional fifth (work: updates per iteration) and, for
+asynchronous executors (``depth`` > 0), three more (in_flight, finished, wait), so its
+admission, policy and retirement logic is tested on the CPU with fake executors and a fake
 clock.
 
 ``python -m paper_2401_09283_amd.serve`` runs the synthetic serving workload (Poisson
-arrivals at 2 requests/s drawn from 128^3 x 248, 256^3 x 496 and 384^3 x 496 views, 30
-iterations each) batched and as sequential plain solves, and prints latency percentiles
-and throughput of both.
+arrivals drawn from 128^3 x 248, 256^3 x 496 and 384^3 x 496 views, 30 iterations each)
+served and as sequential plain solves, and prints latency percentiles and throughput of both.
 """
 from __future__ import annotations
 
+import collections
 import dataclasses
 import json
 import math
+import sys
 import time
 from typing import Callable
 
@@ -65,7 +74,7 @@ class Server:
     """Continuous batching over an executor (see module docstring)."""
 
     def __init__(self, executor, hbm_budget_bytes: int, max_active: int = 16, clock=None, sleep=None,
-                 policy: str = "srpt", tick_work: float = 8e9, max_wait: float | None = None):
+                 policy: str = "srpt", tick_work: float = 8e9, max_wait: float | None = None, min_batch: int = 1):
         if policy not in ("all", "srpt"):
             raise ValueError("policy must be 'all' or 'srpt'")
         self.ex = executor
@@ -74,6 +83,9 @@ class Server:
         self.policy = policy
         self.tick_work = float(tick_work)
         self.max_wait = None if max_wait is None else float(max_wait)
+        self.min_batch = max(1, int(min_batch))
+        # asynchronous executors enqueue work and report completion through in_flight/finished/wait
+        self.depth = int(getattr(executor, "depth", 0) or 0)
         self._now = lambda: 0.0
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
@@ -137,11 +149,20 @@ class Server:
                 r.t_admit = now()
                 r.status = "active"
                 active.append(r)
+            if self.depth:
+                active = self._retire_finished(active, now)
             if not active:
                 if pending:
                     self.sleep(max(0.0, pending[0].arrival - now()))
                 continue
-            batch = self._pick(active)
+            # the policy chooses among the requests with iterations left; of those, a tick enqueues
+            # the ones with fewer than `depth` iterations in flight (asynchronous executors), and
+            # waits for the device when none can take more
+            chosen = self._pick([r for r in active if r.iters_done < r.n_iter])
+            batch = [r for r in chosen if not self.depth or self.ex.in_flight(r) < self.depth]
+            if not batch:
+                self.ex.wait([r for r in (chosen or active) if r.iters_done > 0])
+                continue
             try:
                 self.ex.step(batch)
             except Exception as e:
@@ -153,15 +174,26 @@ class Server:
                 continue
             self.ticks += 1
             self.batch_sizes.append(len(batch))
-            t = now()
             for r in batch:
                 r.iters_done += 1
-                if r.iters_done >= r.n_iter:
-                    r.result = self.ex.result(r)
-                    r.status, r.t_done = "done", t
-                    self._release(r)
-            active = [r for r in active if r.status == "active"]
+            if not self.depth:
+                t = now()
+                for r in batch:
+                    if r.iters_done >= r.n_iter:
+                        self._retire(r, t)
+                active = [r for r in active if r.status == "active"]
         return reqs
+
+    def _retire(self, r, t):
+        r.result = self.ex.result(r)
+        r.status, r.t_done = "done", t
+        self._release(r)
+
+    def _retire_finished(self, active, now):
+        for r in active:
+            if r.iters_done >= r.n_iter and self.ex.finished(r):
+                self._retire(r, now())
+        return [r for r in active if r.status == "active"]
 
     def _work(self, r):
         f = getattr(self.ex, "work", None)
@@ -181,7 +213,7 @@ class Server:
         order = sorted(active, key=key)
         chosen, total = [], 0.0
         for r in order:
-            if chosen and total + self._work(r) > self.tick_work:
+            if len(chosen) >= self.min_batch and total + self._work(r) > self.tick_work:
                 break
             chosen.append(r)
             total += self._work(r)
@@ -210,15 +242,25 @@ def summarize(reqs, t_end=None):
 # ---------------------------------------------------------------------------------- GPU side
 
 class GpuExecutor:
-    """Device state of each admitted request and the batched iteration."""
+    """Device state of each admitted request and the per-tick work.
 
-    def __init__(self, device="cuda", lr=0.05, loss="entropy_tv"):
+    mode "streams" (asynchronous, ``depth`` > 0): every request owns a HIP stream (default
+    priority); a tick enqueues one iteration per ticked request on its stream and records an
+    event, and the server polls the events. mode "batched": a tick is one backprojection launch
+    and one VJP launch over all ticked requests, then a device synchronisation."""
+
+    def __init__(self, device="cuda", lr=0.05, loss="entropy_tv", mode="streams", depth=2, poll_s=50e-6):
         import torch
 
+        if mode not in ("streams", "batched"):
+            raise ValueError("mode must be 'streams' or 'batched'")
         self.torch = torch
         self.device = torch.device(device)
         self.lr = lr
         self.loss = loss
+        self.mode = mode
+        self.depth = int(depth) if mode == "streams" else 0
+        self.poll_s = float(poll_s)
 
     def _inputs(self, r):
         if callable(r.inputs):
@@ -255,10 +297,26 @@ class GpuExecutor:
                            inp["P"], weighting=g.weighting, grad_mode=g.grad_mode, device=self.device)
         proj = torch.from_numpy(inp["proj"]).to(self.device)
         s = MotionSolver(bp, proj, SolverConfig(n_iter=r.n_iter, n_nodes=inp["n_nodes"], lr=self.lr, loss=self.loss))
-        s.calibrate()
+        if self.depth:
+            r.stream = torch.cuda.Stream(device=self.device)
+            r.stream.wait_stream(torch.cuda.current_stream(self.device))   # inputs were copied there
+            r.events = collections.deque()
+            with torch.cuda.stream(r.stream):
+                s.calibrate()
+        else:
+            s.calibrate()
         r.state = s
 
     def step(self, reqs):
+        if self.depth:
+            torch = self.torch
+            for r in reqs:
+                with torch.cuda.stream(r.stream):
+                    r.state.iteration()
+                    ev = torch.cuda.Event()
+                    ev.record(r.stream)
+                    r.events.append(ev)
+            return
         from . import gmc
 
         fwd, vjp = [], []
@@ -283,22 +341,54 @@ class GpuExecutor:
             gmc.gmc_adam_step(s.coeffs, s.gc, s.m, s.v, s.it, s.cfg.lr, s.cfg.beta1, s.cfg.beta2, s.cfg.adam_eps)
         self.torch.cuda.synchronize()
 
-    def result(self, r):
-        from . import gmc
+    # asynchronous mode: completion of enqueued iterations
+    def in_flight(self, r):
+        ev = r.events
+        while ev and ev[0].query():
+            ev.popleft()
+        return len(ev)
 
+    def finished(self, r):
+        return self.in_flight(r) == 0
+
+    def wait(self, reqs):
+        """Return once some enqueued iteration of reqs has completed (polling, host idle)."""
+        import time as _time
+
+        counts = [self.in_flight(r) for r in reqs]
+        if not any(counts):
+            return
+        while True:
+            for r, n in zip(reqs, counts):
+                if self.in_flight(r) < n:
+                    return
+            _time.sleep(self.poll_s)
+
+    def result(self, r):
         s = r.state
+        if self.depth:
+            r.stream.synchronize()
+            with self.torch.cuda.stream(r.stream):
+                s._theta()
+                out = dict(coeffs=s.coeffs.cpu().numpy(), theta=s.theta.cpu().numpy())
+            return out
         s._theta()
         return dict(coeffs=s.coeffs.cpu().numpy(), theta=s.theta.cpu().numpy())
 
     def release(self, r):
+        # the request's stream must be idle before its memory can be reused on another stream
+        if getattr(r, "stream", None) is not None:
+            r.stream.synchronize()
         r.state = None
+        r.stream = None
+        r.events = None
 
 
 def run_sequential(requests, device="cuda", lr=0.05, loss="entropy_tv", clock=None, sleep=None):
     """Plain solves one after another in arrival order (single-request launches)."""
     import torch
 
-    ex = GpuExecutor(device, lr, loss)
+    ex = GpuExecutor(device, lr, loss, mode="batched")   # synchronous: admit and result on the current stream
     clock = clock or time.perf_counter
     sleep = sleep or time.sleep
     reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -362,11 +452,16 @@ def main(argv=None):
     ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--skip-sequential", action="store_true")
-    ap.add_argument("--policy", choices=("all", "srpt", "both"), default="both",
+    ap.add_argument("--mode", choices=("streams", "batched", "both"), default="streams",
+                    help="executor: requests on their own streams, or lockstep batched launches")
+    ap.add_argument("--policy", choices=("all", "srpt", "both"), default="srpt",
                     help="which active requests a tick advances (both: run the two policies)")
     ap.add_argument("--tick-work", type=float, default=8e9, help="srpt: voxel-view updates per tick")
+    ap.add_argument("--min-batch", type=int, default=2, help="srpt: requests per tick while that many are active")
+    ap.add_argument("--depth", type=int, default=2, help="streams: iterations a request may have in flight")
     ap.add_argument("--max-wait", type=float, default=10.0,
                     help="srpt: requests older than this many seconds go first (<= 0: never)")
+    ap.add_argument("--out", default=None, help="also write the JSON summary to this file")
     args = ap.parse_args(argv)
 
     spec = poisson_requests(args.requests, args.rate, args.seed, args.iters)
@@ -384,7 +479,7 @@ def main(argv=None):
         return [Request(rid, arr, it, dict(inputs[rid])) for rid, arr, size, it in spec]
 
     # warm the kernels once
-    warm = GpuExecutor()
+    warm = GpuExecutor(mode="batched")
     w = Request(-1, 0.0, 1, dict(inputs[0]))
     warm.admit(w)
     warm.step([w])
@@ -394,22 +489,27 @@ def main(argv=None):
     out = dict(requests=args.requests, rate_per_s=args.rate, iters=args.iters, seed=args.seed,
                sizes={s: sum(1 for x in spec if x[2] == s) for s in SERVE_SIZES})
     policies = ("all", "srpt") if args.policy == "both" else (args.policy,)
+    modes = ("streams", "batched") if args.mode == "both" else (args.mode,)
     runs = {}
-    for pol in policies:
-        srv = Server(GpuExecutor(), int(args.budget_gb * 1e9), args.max_active, policy=pol, tick_work=args.tick_work,
-                     max_wait=args.max_wait if args.max_wait > 0 else None)
-        reqs = srv.run(fresh())
-        key = "batched" if pol == "all" else "batched_" + pol
-        out[key] = summarize(reqs)
-        out[key]["policy"] = pol
-        if pol == "srpt":
-            out[key]["max_wait_s"] = args.max_wait if args.max_wait > 0 else None
-        out[key]["mean_batch"] = float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0
-        out[key]["rpe_final_mm_mean"] = float(np.mean([
-            reprojection_error(inputs[r.rid]["P"], r.result["theta"], inputs[r.rid]["theta_true"],
-                               _pitch(inputs[r.rid]["size"])) for r in reqs if r.status == "done"]))
-        runs[pol] = reqs
-        print("serve: %s %s" % (key, json.dumps(out[key])), flush=True)
+    for mode in modes:
+        for pol in policies:
+            ex = GpuExecutor(mode=mode, depth=args.depth)
+            srv = Server(ex, int(args.budget_gb * 1e9), args.max_active, policy=pol, tick_work=args.tick_work,
+                         max_wait=args.max_wait if args.max_wait > 0 else None, min_batch=args.min_batch)
+            reqs = srv.run(fresh())
+            key = "served_%s_%s" % (mode, pol)
+            out[key] = summarize(reqs)
+            out[key].update(mode=mode, policy=pol, mean_batch=float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0)
+            if pol == "srpt":
+                out[key].update(max_wait_s=args.max_wait if args.max_wait > 0 else None, min_batch=args.min_batch,
+                                tick_work=args.tick_work)
+            if mode == "streams":
+                out[key]["depth"] = args.depth
+            out[key]["rpe_final_mm_mean"] = float(np.mean([
+                reprojection_error(inputs[r.rid]["P"], r.result["theta"], inputs[r.rid]["theta_true"],
+                                   _pitch(inputs[r.rid]["size"])) for r in reqs if r.status == "done"]))
+            runs[key] = reqs
+            print("serve: %s %s" % (key, json.dumps(out[key])), flush=True)
     if not args.skip_sequential:
         print("serve: sequential plain solves", flush=True)
         seq = run_sequential(fresh())
@@ -430,7 +530,11 @@ def main(argv=None):
     out["rpe_initial_mm_mean"] = float(np.mean([
         reprojection_error(inputs[i]["P"], np.zeros_like(inputs[i]["theta_true"]), inputs[i]["theta_true"],
                            _pitch(inputs[i]["size"])) for i in range(len(spec))]))
+    out["command"] = "python -m paper_2401_09283_amd.serve " + " ".join(argv if argv is not None else sys.argv[1:])
     print(json.dumps(out), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(out, f, indent=1)
 
 
 def _pitch(size):

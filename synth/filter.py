@@ -1,8 +1,9 @@
 """FDK pre-filtering of line integrals: cosine weight, Parker short-scan weight, ramp filter.
 
-The paper applies "a ramp filter and a cosine filter" (Sec. III) and, for the
-200-degree clinical short scans, Parker weights (Sec. V). It does not print
-the formulas, so the textbook forms are used:
+The paper filters its projections with a ramp kernel and weights them with a
+cosine term (Sec. III), and uses Parker weights for the 200-degree clinical
+short scans (Sec. V). It does not print the formulas, so the textbook forms
+are used:
 
 * Work on the virtual detector through the isocentre: spacing
   tau = pitch * D_so / D_sd, coordinates a = (c - c0) tau, b = (r - r0) tau.

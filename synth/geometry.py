@@ -5,8 +5,8 @@ homogeneous world points to homogeneous detector points, unique up to scale
 (Sec. II-A; Sec. II-B.1). It does not fix a coordinate convention, so this
 module fixes one:
 
-* World origin at the isocentre; the source rotates in the x-y plane
-  (the "plane in which the source rotates" of Fig. 4's caption).
+* World origin at the isocentre; the source rotates in the x-y plane (the
+  source's plane of rotation is the reference plane of Fig. 4).
 * View j has source angle beta_j = j * arc / n_views (counter-clockwise),
   source S = D_so (cos b, sin b, 0).
 * Detector frame: e_u = (-sin b, cos b, 0), e_v = (0, 0, 1),

@@ -1,5 +1,6 @@
 """Serving on the GPU: one batched launch over several geometries gives bitwise the same
-results as the single calls, and a request's solve is the same alone and in the mix."""
+results as the single calls, and a request's solve is the same alone and in the mix, with
+requests on their own streams or in lockstep batched launches."""
 import dataclasses
 
 import numpy as np
@@ -83,22 +84,30 @@ def _req_inputs(i):
     return dict(geometry=g, proj=c.proj, P=c.P, n_nodes=cfg.n_nodes)
 
 
-@pytest.mark.parametrize("policy", ["all", "srpt"])
-def test_served_results_equal_solo_solves(policy):
+def _solo(inputs, n_iter):
+    """A plain solve: the solver's own iterations on the current stream."""
+    solo = Request(100, 0.0, n_iter, dict(inputs))
+    ex = GpuExecutor(mode="batched")
+    ex.admit(solo)
+    s = solo.state
+    for _ in range(n_iter):
+        s.iteration()
+    return ex.result(solo)
+
+
+@pytest.mark.parametrize("mode,policy", [("streams", "srpt"), ("streams", "all"), ("batched", "srpt"),
+                                         ("batched", "all")])
+def test_served_results_equal_solo_solves(mode, policy):
     inputs = [_req_inputs(i) for i in range(4)]
     reqs = [Request(i, 0.0 if i < 2 else 0.002 * i, 6 + i, dict(inputs[i])) for i in range(4)]
-    # srpt with a tick budget of about two of these requests: some ticks share launches, some not
-    srv = Server(GpuExecutor(), hbm_budget_bytes=int(50e9), max_active=3, policy=policy, tick_work=2.6e7)
+    # srpt with a tick budget of about two of these requests: some ticks share the GPU, some not
+    ex = GpuExecutor(mode=mode)
+    srv = Server(ex, hbm_budget_bytes=int(50e9), max_active=3, policy=policy, tick_work=2.6e7)
     done = srv.run(reqs)
     s = summarize(done)
-    print("[serve] %s mean batch %.2f" % (s, np.mean(srv.batch_sizes)), flush=True)
+    print("[serve %s/%s] %s mean batch %.2f" % (mode, policy, s, np.mean(srv.batch_sizes)), flush=True)
     assert s["done"] == 4
-    assert max(srv.batch_sizes) > 1          # requests did share launches
+    assert max(srv.batch_sizes) > 1          # requests did share ticks
     for r in done:
-        solo = Request(100 + r.rid, 0.0, r.n_iter, dict(inputs[r.rid]))
-        ex = GpuExecutor()
-        ex.admit(solo)
-        for _ in range(r.n_iter):
-            ex.step([solo])
-        res = ex.result(solo)
+        res = _solo(inputs[r.rid], r.n_iter)
         assert np.array_equal(res["coeffs"], r.result["coeffs"]), r.rid

@@ -216,3 +216,68 @@ def test_cancellation_frees_the_slot_and_the_memory():
     assert adm2 > rel0
     assert srv.used == 0 and not ex.resident
     assert sum(1 for e in ex.log if e[0] == "step" and 0 in e[1]) == 2
+
+
+class FakeAsyncExecutor(FakeExecutor):
+    """Enqueues iterations on a simulated device that runs them one after another (each takes
+    the request's `cost` seconds of device time); completion is seen through the fake clock."""
+
+    depth = 2
+
+    def __init__(self, clock):
+        super().__init__(clock)
+        self.device_free = 0.0
+        self.jobs = {}          # rid -> completion times of enqueued iterations
+        self.max_in_flight = 0
+
+    def step(self, reqs):
+        self.steps += 1
+        self.log.append(("step", tuple(r.rid for r in reqs), self.clock()))
+        for r in reqs:
+            assert self.in_flight(r) < self.depth
+            start = max(self.device_free, self.clock())
+            self.device_free = start + r.inputs.get("cost", 0.1)
+            self.jobs.setdefault(r.rid, []).append(self.device_free)
+            self.max_in_flight = max(self.max_in_flight, self.in_flight(r))
+        self.clock.t += 1e-4   # host time to enqueue
+
+    def in_flight(self, r):
+        return sum(1 for t in self.jobs.get(r.rid, []) if t > self.clock())
+
+    def finished(self, r):
+        return self.in_flight(r) == 0
+
+    def wait(self, reqs):
+        pending = [t for r in reqs for t in self.jobs.get(r.rid, []) if t > self.clock()]
+        assert pending, "wait() with nothing in flight"
+        self.clock.t = min(pending)
+
+    def result(self, r):
+        assert self.finished(r)
+        return {"rid": r.rid, "t_last": max(self.jobs[r.rid])}
+
+
+def test_asynchronous_executor_keeps_depth_and_retires_after_the_device():
+    clk = FakeClock()
+    ex = FakeAsyncExecutor(clk)
+    srv = Server(ex, hbm_budget_bytes=100, max_active=3, clock=clk, sleep=clk.sleep, policy="srpt", tick_work=3.0,
+                 min_batch=2)
+    reqs = [Request(0, 0.0, 4, {"bytes": 40, "work": 10.0, "cost": 0.2}),
+            Request(1, 0.0, 3, {"bytes": 40, "work": 1.0, "cost": 0.05}),
+            Request(2, 0.01, 2, {"bytes": 40, "work": 1.0, "cost": 0.05}),
+            Request(3, 0.5, 2, {"bytes": 10, "work": 1.0, "cost": 0.05})]
+    done = srv.run(reqs)
+    assert all(r.status == "done" and r.iters_done == r.n_iter for r in done)
+    assert ex.max_in_flight <= FakeAsyncExecutor.depth
+    for r in done:
+        # a request retires only once its last iteration has finished on the device
+        assert r.t_done >= r.result["t_last"] - 1e-12
+        assert len(ex.jobs[r.rid]) == r.n_iter
+    # request 2 (40 B) could only be admitted after one of the first two retired
+    adm2 = next(i for i, e in enumerate(ex.log) if e[0] == "admit" and e[1] == 2)
+    first_rel = next(i for i, e in enumerate(ex.log) if e[0] == "release")
+    assert adm2 > first_rel
+    assert srv.used == 0 and not ex.resident
+    # min_batch: while two requests were active, ticks took two even beyond the work budget
+    steps = [e[1] for e in ex.log if e[0] == "step"]
+    assert steps[0] == (0, 1)
