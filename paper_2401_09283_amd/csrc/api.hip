@@ -118,8 +118,8 @@ struct WS {
     float* part;
     double* G;
     int* status;
-    double* loss;
-    double* hist;
+    float* loss;
+    float* hist;
     float* vpart;
 };
 
@@ -132,8 +132,8 @@ WS carve(const gmc_plan* p, void* ws) {
     w.part = (float*)(b + p->off_part);
     w.G = (double*)(b + p->off_G);
     w.status = (int*)(b + p->off_status);
-    w.loss = (double*)(b + p->off_loss);
-    w.hist = (double*)(b + p->off_hist);
+    w.loss = (float*)(b + p->off_loss);
+    w.hist = (float*)(b + p->off_hist);
     w.vpart = (float*)(b + p->off_vpart);
     return w;
 }
@@ -276,8 +276,8 @@ gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_p
     p->off_part = off; off = align256(off + n * (size_t)nb * PART_STRIDE * sizeof(float));
     p->off_G = off; off = align256(off + n * 12 * sizeof(double));
     p->off_status = off; off = align256(off + sizeof(int));
-    p->off_loss = off; off = align256(off + (4 * (size_t)LOSS_BLOCKS + 8) * sizeof(double));
-    p->off_hist = off; off = align256(off + ((size_t)HIST_BINS * HIST_BLOCKS + 2 * HIST_BINS + 8) * sizeof(double));
+    p->off_loss = off; off = align256(off + (4 * (size_t)LOSS_BLOCKS + 8) * sizeof(float));
+    p->off_hist = off; off = align256(off + ((size_t)HIST_BINS * HIST_BLOCKS + 2 * HIST_BINS + 8) * sizeof(float));
     p->off_vpart = off;
     off = align256(off + (size_t)(p->vsplit_fwd - 1) * (size_t)g->nx * g->ny * g->nz * sizeof(float));
     p->ws_bytes = off;

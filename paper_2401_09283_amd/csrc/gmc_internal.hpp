@@ -110,10 +110,10 @@ hipError_t launch_reduce_chain(const gmc_plan* p, const float* part, const doubl
                                double* grad_theta, double* grad_P, hipStream_t s);
 hipError_t launch_debug_project(const gmc_plan* p, const BrickDesc* desc, long long n, const int64_t* voxel,
                                 const int32_t* view, int32_t* cell, float* frac, hipStream_t s);
-hipError_t launch_loss_sumsq(const gmc_plan* p, const float* vol, float* grad, double* scratch, double* loss,
+hipError_t launch_loss_sumsq(const gmc_plan* p, const float* vol, float* grad, float* scratch, double* loss,
                              hipStream_t s);
 hipError_t launch_loss_entropy_tv(const gmc_plan* p, const float* vol, double lambda, double lo, double hi,
-                                  double eps, float* grad, double* scratch, double* hist, double* loss,
+                                  double eps, float* grad, float* scratch, float* hist, double* loss,
                                   hipStream_t s);
 hipError_t launch_bspline_theta(int n_views, int n_nodes, const double* coeffs, double* theta, hipStream_t s);
 hipError_t launch_bspline_grad(int n_views, int n_nodes, const double* grad_theta, double* grad_coeffs,

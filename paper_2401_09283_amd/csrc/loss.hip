@@ -4,15 +4,16 @@
 //   * sum of squared forward differences between neighbouring voxels;
 //   * soft-histogram entropy (64 bins, cubic B-spline Parzen window) plus lambda * total
 //     variation (forward differences, a difference leaving the grid counts as 0).
-// Voxel arithmetic is FP32; scalar sums and the 64-bin histogram are accumulated in FP64 in
-// a fixed order (per-thread, per-block, then one final block), so results are reproducible.
+// Arithmetic and accumulation are FP32: every scalar sum and the 64-bin histogram are
+// accumulated per thread, then by fixed-order trees over the block and over the blocks, so the
+// results are reproducible. Only the ABI's loss words are FP64 (converted at the end).
 #include "gmc_internal.hpp"
 
 namespace gmc {
 
 namespace {
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
+__device__ __forceinline__ float block_sum(float v, float* sh) {
     const int t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
@@ -20,7 +21,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
         if (t < s) sh[t] += sh[t + s];
         __syncthreads();
     }
-    const double r = sh[0];
+    const float r = sh[0];
     __syncthreads();
     return r;
 }
@@ -58,10 +59,10 @@ __device__ __forceinline__ float db3(float s) {
         for (int k = threadIdx.x; k < (nz); k += 256)
 
 __global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ I, float* __restrict__ grad,
-                                               double* __restrict__ part, int nx, int ny, int nz) {
-    __shared__ double sh[256];
+                                               float* __restrict__ part, int nx, int ny, int nz) {
+    __shared__ float sh[256];
     const long long sx = (long long)ny * nz, sy = nz;
-    double local = 0.0;
+    float local = 0.0f;
     FOR_EACH_VOXEL(nx, ny, nz) {
         const int i = col / ny, j = col % ny;
         const long long idx = (long long)col * nz + k;
@@ -75,30 +76,38 @@ __global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ I, floa
         if (k + 1 < nz) { const float d = I[idx + 1] - c; s = fmaf(d, d, s); g -= 2.0f * d; }
         if (k > 0) { g += 2.0f * (c - I[idx - 1]); }
         grad[idx] = g;
-        local += (double)s;
+        local += s;
     }
-    const double b = block_sum(local, sh);
+    const float b = block_sum(local, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = b;
 }
 
 // sums nparts partials of each of ncol columns (part[col * nparts + p]) in a fixed order
-__global__ void __launch_bounds__(256) k_sum_cols(const double* __restrict__ part, int nparts, int ncol,
-                                                  double* __restrict__ out) {
-    __shared__ double sh[256];
+__global__ void __launch_bounds__(256) k_sum_cols(const float* __restrict__ part, int nparts, int ncol,
+                                                  float* __restrict__ out) {
+    __shared__ float sh[256];
     for (int col = 0; col < ncol; ++col) {
-        double v = 0.0;
+        float v = 0.0f;
         for (int p = threadIdx.x; p < nparts; p += 256) v += part[(long long)col * nparts + p];
-        const double s = block_sum(v, sh);
+        const float s = block_sum(v, sh);
         if (threadIdx.x == 0) out[col] = s;
     }
 }
 
-hipError_t launch_loss_sumsq(const gmc_plan* p, const float* vol, float* grad, double* scratch, double* loss,
+__global__ void k_to_double(const float* __restrict__ src, double* __restrict__ dst, int n) {
+    const int i = threadIdx.x;
+    if (i < n) dst[i] = (double)src[i];
+}
+
+hipError_t launch_loss_sumsq(const gmc_plan* p, const float* vol, float* grad, float* scratch, double* loss,
                              hipStream_t s) {
     k_sumsq<<<LOSS_BLOCKS, 256, 0, s>>>(vol, grad, scratch, p->g.nx, p->g.ny, p->g.nz);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_sum_cols<<<1, 256, 0, s>>>(scratch, LOSS_BLOCKS, 1, loss);
+    float* total = scratch + LOSS_BLOCKS;
+    k_sum_cols<<<1, 256, 0, s>>>(scratch, LOSS_BLOCKS, 1, total);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_to_double<<<1, 64, 0, s>>>(total, loss, 1);
     return hipGetLastError();
 }
 
@@ -109,8 +118,9 @@ struct HistArgs {
     float lo, inv_d;
 };
 
-// per-thread private histograms in LDS ([bin][thread], conflict free), summed per block in FP64
-__global__ void __launch_bounds__(256) k_hist(HistArgs a, double* __restrict__ hist_part) {
+// per-thread private histograms in LDS ([bin][thread], conflict free), summed per block by a
+// fixed-order tree (thread t of the first 64 sums bin t)
+__global__ void __launch_bounds__(256) k_hist(HistArgs a, float* __restrict__ hist_part) {
     __shared__ float h[HIST_BINS * 256];
     const int t = threadIdx.x;
     for (int b = 0; b < HIST_BINS; ++b) h[b * 256 + t] = 0.0f;
@@ -126,41 +136,50 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a, double* __restrict__ h
         }
     }
     __syncthreads();
-    if (t < HIST_BINS) {
-        double sum = 0.0;
-        for (int q = 0; q < 256; ++q) sum += (double)h[t * 256 + q];
-        hist_part[(long long)t * gridDim.x + blockIdx.x] = sum;
+    // pairwise tree over the 256 threads' histograms, all 64 bins at once
+    for (int w = 128; w > 0; w >>= 1) {
+        for (int e = t; e < HIST_BINS * w; e += 256) {
+            const int b = e / w, q = e % w;
+            h[b * 256 + q] += h[b * 256 + q + w];
+        }
+        __syncthreads();
     }
+    if (t < HIST_BINS) hist_part[(long long)t * gridDim.x + blockIdx.x] = h[t * 256];
 }
 
 // hist[b] = sum over blocks of the per-block partials (one block per bin, fixed-order tree)
-__global__ void __launch_bounds__(256) k_hist_reduce(const double* __restrict__ hist_part, int nparts,
-                                                     double* __restrict__ hist) {
-    __shared__ double sh[256];
+__global__ void __launch_bounds__(256) k_hist_reduce(const float* __restrict__ hist_part, int nparts,
+                                                     float* __restrict__ hist) {
+    __shared__ float sh[256];
     const int b = blockIdx.x;
-    double v = 0.0;
+    float v = 0.0f;
     for (int p = threadIdx.x; p < nparts; p += 256) v += hist_part[(long long)b * nparts + p];
-    const double s = block_sum(v, sh);
+    const float s = block_sum(v, sh);
     if (threadIdx.x == 0) hist[b] = s;
 }
 
-// coef[64..127] = dH/dh_b; hist[128] = H
-__global__ void __launch_bounds__(64) k_hist_final(double* __restrict__ hist) {
-    __shared__ double sh[64];
+// coef[64..127] = dH/dh_b; hist[128] = H (sums over the bins by fixed-order trees)
+__global__ void __launch_bounds__(64) k_hist_final(float* __restrict__ hist) {
+    __shared__ float sh[64], zs[64], hs[64];
     const int b = threadIdx.x;
-    const double h = hist[b];
+    const float h = hist[b];
     sh[b] = h;
+    zs[b] = h;
     __syncthreads();
-    double Z = 0.0;
-    for (int q = 0; q < HIST_BINS; ++q) Z += sh[q];
-    double H = 0.0;
-    for (int q = 0; q < HIST_BINS; ++q)
-        if (sh[q] > 0.0) {
-            const double pq = sh[q] / Z;
-            H -= pq * log(pq);
-        }
-    double coef = 0.0;
-    if (h > 0.0 && Z > 0.0) coef = -(log(h / Z) + H) / Z;
+    for (int w = 32; w > 0; w >>= 1) {
+        if (b < w) zs[b] += zs[b + w];
+        __syncthreads();
+    }
+    const float Z = zs[0];
+    hs[b] = (h > 0.0f && Z > 0.0f) ? -(h / Z) * logf(h / Z) : 0.0f;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (b < w) hs[b] += hs[b + w];
+        __syncthreads();
+    }
+    const float H = hs[0];
+    float coef = 0.0f;
+    if (h > 0.0f && Z > 0.0f) coef = -(logf(h / Z) + H) / Z;
     hist[HIST_BINS + b] = coef;
     if (b == 0) hist[2 * HIST_BINS] = H;
 }
@@ -168,8 +187,8 @@ __global__ void __launch_bounds__(64) k_hist_final(double* __restrict__ hist) {
 struct GradArgs {
     const float* I;
     float* grad;
-    const double* hist;   // coef at [64..127]
-    double* part;         // [3][nblocks]: TV, |gH|^2, |gTV|^2
+    const float* hist;    // coef at [64..127]
+    float* part;          // [3][nblocks]: TV, |gH|^2, |gTV|^2
     int nx, ny, nz;
     float lo, inv_d, eps2, lambda;
 };
@@ -186,11 +205,11 @@ __device__ __forceinline__ float tv_norm(const float* __restrict__ I, long long 
 
 __global__ void __launch_bounds__(256) k_entropy_tv_grad(GradArgs a) {
     __shared__ float coef[HIST_BINS];
-    __shared__ double sh[256];
-    if (threadIdx.x < HIST_BINS) coef[threadIdx.x] = (float)a.hist[HIST_BINS + threadIdx.x];
+    __shared__ float sh[256];
+    if (threadIdx.x < HIST_BINS) coef[threadIdx.x] = a.hist[HIST_BINS + threadIdx.x];
     __syncthreads();
     const long long sx = (long long)a.ny * a.nz, sy = a.nz;
-    double tv = 0.0, gh2 = 0.0, gt2 = 0.0;
+    float tv = 0.0f, gh2 = 0.0f, gt2 = 0.0f;
     FOR_EACH_VOXEL(a.nx, a.ny, a.nz) {
         const int i = col / a.ny, j = col % a.ny;
         const long long idx = (long long)col * a.nz + k;
@@ -216,13 +235,13 @@ __global__ void __launch_bounds__(256) k_entropy_tv_grad(GradArgs a) {
         if (j > 0) { const float nn = tv_norm(a.I, idx - sy, i, j - 1, k, a.nx, a.ny, a.nz, sx, sy, a.eps2, p, q, r); gt += q / nn; }
         if (k > 0) { const float nn = tv_norm(a.I, idx - 1, i, j, k - 1, a.nx, a.ny, a.nz, sx, sy, a.eps2, p, q, r); gt += r / nn; }
         a.grad[idx] = fmaf(a.lambda, gt, gh);
-        tv += (double)n0;
-        gh2 += (double)gh * (double)gh;
-        gt2 += (double)gt * (double)gt;
+        tv += n0;
+        gh2 = fmaf(gh, gh, gh2);
+        gt2 = fmaf(gt, gt, gt2);
     }
-    const double b0 = block_sum(tv, sh);
-    const double b1 = block_sum(gh2, sh);
-    const double b2 = block_sum(gt2, sh);
+    const float b0 = block_sum(tv, sh);
+    const float b1 = block_sum(gh2, sh);
+    const float b2 = block_sum(gt2, sh);
     if (threadIdx.x == 0) {
         a.part[blockIdx.x] = b0;
         a.part[gridDim.x + blockIdx.x] = b1;
@@ -230,25 +249,25 @@ __global__ void __launch_bounds__(256) k_entropy_tv_grad(GradArgs a) {
     }
 }
 
-__global__ void k_entropy_tv_final(const double* __restrict__ sums, const double* __restrict__ hist, double lambda,
+__global__ void k_entropy_tv_final(const float* __restrict__ sums, const float* __restrict__ hist, float lambda,
                                    double* __restrict__ loss) {
-    const double H = hist[2 * HIST_BINS];
-    loss[0] = H + lambda * sums[0];
-    loss[1] = H;
-    loss[2] = sums[0];
-    loss[3] = sums[1];
-    loss[4] = sums[2];
+    const float H = hist[2 * HIST_BINS];
+    loss[0] = (double)fmaf(lambda, sums[0], H);
+    loss[1] = (double)H;
+    loss[2] = (double)sums[0];
+    loss[3] = (double)sums[1];
+    loss[4] = (double)sums[2];
 }
 
 hipError_t launch_loss_entropy_tv(const gmc_plan* p, const float* vol, double lambda, double lo, double hi,
-                                  double eps, float* grad, double* scratch, double* hist, double* loss,
+                                  double eps, float* grad, float* scratch, float* hist, double* loss,
                                   hipStream_t s) {
     const long long N = (long long)p->g.nx * p->g.ny * p->g.nz;
     const float inv_d = (float)((double)HIST_BINS / (hi - lo));
     HistArgs ha{vol, N, (float)lo, inv_d};
     // hist scratch: [64][HIST_BLOCKS] partials, then 129 finals
-    double* hist_part = hist;
-    double* hist_final = hist + (long long)HIST_BINS * HIST_BLOCKS;
+    float* hist_part = hist;
+    float* hist_final = hist + (long long)HIST_BINS * HIST_BLOCKS;
     k_hist<<<HIST_BLOCKS, 256, 0, s>>>(ha, hist_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -270,10 +289,10 @@ hipError_t launch_loss_entropy_tv(const gmc_plan* p, const float* vol, double la
     ga.lambda = (float)lambda;
     k_entropy_tv_grad<<<LOSS_BLOCKS, 256, 0, s>>>(ga);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    double* sums = scratch + 3 * LOSS_BLOCKS;
+    float* sums = scratch + 3 * LOSS_BLOCKS;
     k_sum_cols<<<1, 256, 0, s>>>(scratch, LOSS_BLOCKS, 3, sums);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_entropy_tv_final<<<1, 1, 0, s>>>(sums, hist_final, lambda, loss);
+    k_entropy_tv_final<<<1, 1, 0, s>>>(sums, hist_final, (float)lambda, loss);
     return hipGetLastError();
 }
 

@@ -1,8 +1,9 @@
 // Finishing the Jacobian-vector product: the per-(view, brick) partials of G_j, taken in each
 // brick's local frame, are moved back to the frame of Phat_j and summed over bricks in a
-// fixed order, giving G_j = dL/dPhat_j; Eq. 2 then contracts G_j with the derivative
-// matrices P_j dT_j/dtheta_jk. This forms dL/dPhat_j itself, so it runs in FP64 like the
-// matrix composition.
+// fixed order (per-thread strided sums, then a pairwise tree over the block), giving
+// G_j = dL/dPhat_j; Eq. 2 then contracts G_j with the derivative matrices P_j dT_j/dtheta_jk.
+// The frame change and the sum are FP32 like the rest of the voxel arithmetic; the
+// contraction with the FP64 derivative matrices, and the outputs, are FP64.
 //
 // Frame change: the kernels differentiate with respect to M = S Phat T_b, where T_b moves
 // brick-local points to the world (origin o_b) and S = [[1,0,-ou],[0,1,-ov],[0,0,1]] shifts
@@ -23,30 +24,31 @@ struct ReduceArgs {
 };
 
 __global__ void __launch_bounds__(256) k_reduce_chain(ReduceArgs a) {
-    __shared__ double sh[256 * 12];
+    __shared__ float sh[256 * 12];
+    __shared__ double shd[12];
     const int v = blockIdx.x;
     const int t = threadIdx.x;
-    double acc[12];
+    float acc[12];
 #pragma unroll
-    for (int e = 0; e < 12; ++e) acc[e] = 0.0;
+    for (int e = 0; e < 12; ++e) acc[e] = 0.0f;
     for (int b = t; b < a.n_bricks; b += 256) {
         const float* p = a.part + ((long long)v * a.n_bricks + b) * PART_STRIDE;
         float q[14];
 #pragma unroll
         for (int e = 0; e < 14; ++e) q[e] = p[e];
-        const double ou = (double)__float_as_int(q[12]);
-        const double ov = (double)__float_as_int(q[13]);
+        const float ou = (float)__float_as_int(q[12]);
+        const float ov = (float)__float_as_int(q[13]);
         const int bj = b % a.nby;
         const int bi = (b / a.nby) % a.nbx;
         const int bk = b / (a.nby * a.nbx);
-        const double o[3] = {a.ox + (double)(bi * BXY) * a.dx, a.oy + (double)(bj * BXY) * a.dy,
-                             a.oz + (double)(bk * a.bz) * a.dz};
-        double g[12];
+        const float o[3] = {(float)(a.ox + (double)(bi * BXY) * a.dx), (float)(a.oy + (double)(bj * BXY) * a.dy),
+                            (float)(a.oz + (double)(bk * a.bz) * a.dz)};
+        float g[12];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            g[c] = (double)q[c];
-            g[4 + c] = (double)q[4 + c];
-            g[8 + c] = (double)q[8 + c] - ou * (double)q[c] - ov * (double)q[4 + c];
+            g[c] = q[c];
+            g[4 + c] = q[4 + c];
+            g[8 + c] = q[8 + c] - ou * q[c] - ov * q[4 + c];
         }
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
@@ -66,7 +68,8 @@ __global__ void __launch_bounds__(256) k_reduce_chain(ReduceArgs a) {
         __syncthreads();
     }
     if (t < 12) {
-        const double gv = sh[t * 256];
+        const double gv = (double)sh[t * 256];
+        shd[t] = gv;
         a.G[12 * v + t] = gv;
         if (a.grad_P) a.grad_P[12 * v + t] = gv;
     }
@@ -74,7 +77,7 @@ __global__ void __launch_bounds__(256) k_reduce_chain(ReduceArgs a) {
     if (t < 6) {
         const double* D = a.dPhat + 72 * v + 12 * t;
         double s = 0.0;
-        for (int e = 0; e < 12; ++e) s += sh[e * 256] * D[e];
+        for (int e = 0; e < 12; ++e) s += shd[e] * D[e];
         a.grad_theta[6 * v + t] = s;
     }
 }
