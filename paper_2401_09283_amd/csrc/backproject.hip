@@ -170,14 +170,15 @@ __device__ __forceinline__ unsigned lds_index(unsigned base, unsigned bytes, flo
 }
 __device__ __forceinline__ LdsF* lds_f(unsigned addr) { return (LdsF*)(size_t)addr; }
 
-// LDS address of the sample's cell (row-major, pitch TP), the cell clamped into [lo, hi] so
-// that every tap stays inside the tile buffer (a guard: the tile bounds already contain every
-// sample). The linear cell is formed with the column's 2^23 bias already in place
-// (fv TP + fu + 2^23, exact below 2^24), so its bits give the address without another add.
+// LDS address of the sample's cell (row-major, pitch TP). The linear cell is formed with the
+// column's 2^23 bias already in place (fv TP + fu + 2^23, exact below 2^24), so its bits give
+// the address without another add. No clamp: the tile spans the cells of the brick's projected
+// corners plus one cell of margin on every side (and the halo beyond it), the projection of
+// every voxel of the brick lies inside its corners' hull, and the FP32 positions differ from
+// the set-up's FP64 corners by about 1e-3 pixel, so no cell leaves the margin.
 template <int TP>
-__device__ __forceinline__ unsigned tile_cell(const Cell& c, float lo, float hi, unsigned base) {
-    const float nb = __builtin_amdgcn_fmed3f(fmaf(c.fv, (float)TP, c.fub), lo + TWO23, hi + TWO23);
-    return base + 4u * __float_as_uint(nb);
+__device__ __forceinline__ unsigned tile_cell(const Cell& c, unsigned base) {
+    return base + 4u * __float_as_uint(fmaf(c.fv, (float)TP, c.fub));
 }
 
 // Row coefficients of Eq. 4 for one sample, accumulated into the 6 running sums of the column:
@@ -337,6 +338,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                                          float* __restrict__ sRed) {
     constexpr int NSEG = (TP + 63) / 64;
     static_assert(BZ % FWD_GROUP == 0, "the forward samples a column in whole groups");
+    static_assert(BZ % 4 == 0, "seeds and voxels move in groups of 4 along z");
     static_assert(TP <= 128 && 128 + TH <= THREADS, "border tables: columns by threads 0 .. TP-1, rows by 128 ..");
     const int brick = item % a.n_bricks, chunk = item / a.n_bricks;
     const int v_lo = chunk * a.n_views / a.vsplit, v_hi = (chunk + 1) * a.n_views / a.vsplit;
@@ -346,9 +348,24 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
 
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
-    // each wave covers an 8 x 8 patch of columns, so its samples spread over fewer than 32
-    // detector columns of a tile row (fewer LDS bank conflicts)
-    const int li = 8 * (wave & 1) + (lane >> 3), lj = 8 * (wave >> 1) + (lane & 7);
+    typedef const __attribute__((address_space(4))) BrickDesc ConstDesc;
+    // Each wave covers an 8 x 8 patch of columns and each half-wave (the lanes one LDS pass
+    // serves) 4 (x) by 8 (y) of them, so that a half-wave's samples fall on few detector columns
+    // and rows of a tile (fewer bank conflicts). The VJP transposes the half-wave patches to 8 by
+    // 4 when, at the middle view of its chunk, the detector column moves faster along y than
+    // along x (chunks span a few degrees of the arc; the forward's longer chunks keep 4 by 8).
+    int li = 8 * (wave & 1) + (lane >> 3), lj = 8 * (wave >> 1) + (lane & 7);
+    if (VJP && v_lo < v_hi) {
+        const ConstDesc* dm = (ConstDesc*)(desc + brick) + (long long)((v_lo + v_hi) >> 1) * a.n_bricks;
+        // d(u''/w)/dx and d(u''/w)/dy at the tile's middle column, both times w
+        const float c = 0.5f * (float)dm->tw;
+        const float ax = fabsf(fmaf(-c, dm->m[8], dm->m[0])), ay = fabsf(fmaf(-c, dm->m[9], dm->m[1]));
+        if (dm->mode != TILE_SKIP && ay > ax) {
+            const int tmp = li;
+            li = lj;
+            lj = tmp;
+        }
+    }
     const int i = bi * BXY + li, j = bj * BXY + lj, k0 = bk * BZ;
     const bool col_in = (i < a.nx) && (j < a.ny);
     const float qx = (float)li * a.dx, qy = (float)lj * a.dy, dz = a.dz;
@@ -383,7 +400,6 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
 
     // the descriptors are read-only for the whole launch: read them through the constant
     // address space so that they arrive with scalar loads whatever the caller's pointer provenance
-    typedef const __attribute__((address_space(4))) BrickDesc ConstDesc;
     ConstDesc* descs = (ConstDesc*)(desc + brick);
     const long long dstride = a.n_bricks;
 
@@ -473,7 +489,6 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
 
         if (cur.mode == TILE_INTERIOR) {
             // cell (r, c) with 1 <= r <= rmax, 1 <= c <= cmax: every tap, halo included, in the tile
-            const float lo = (float)(TP + 1), hi = fmaf(rmax, (float)TP, cmax);
             const unsigned base = lds_base(tile, 4u);
             if (!VJP) {
                 // per group of FWD_GROUP samples: positions first, then all LDS reads, then the
@@ -486,7 +501,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                     for (int k = 0; k < FWD_GROUP; ++k) {
                         const Smp p = next_sample(col, g + k);
                         const Cell c = cell_of(p);
-                        off[k] = tile_cell<TP>(c, lo, hi, base);
+                        off[k] = tile_cell<TP>(c, base);
                         au[k] = c.au;
                         av[k] = c.av;
                         ww[k] = (WEIGHT == GMC_WEIGHT_FDK) ? p.rw * p.rw : 1.0f;
@@ -524,7 +539,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                     }
 #pragma unroll
                     for (int i = 0; i < VJP_GROUP; ++i)
-                        load_plain<TP, GRAD, true>(lds_f(tile_cell<TP>(c[i], lo, hi, base_m)), tp[i]);
+                        load_plain<TP, GRAD, true>(lds_f(tile_cell<TP>(c[i], base_m)), tp[i]);
 #pragma unroll
                     for (int i = 0; i < VJP_GROUP; ++i) {
                         float val, gu, gv;
@@ -536,7 +551,6 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
         } else if (cur.mode == TILE_EDGE) {
             // per slice k (uniform branches): skip slices that miss the detector, plain taps for
             // slices inside it, masked taps for the slices across its border
-            const float lo = (float)(TP + 1), hi = fmaf(rmax, (float)TP, cmax);
             const unsigned tb = lds_base(tile, 4u), cb = lds_base(sCol, 8u), rb = lds_base(sRow, 8u);
             const unsigned kin = cur.kin, kout = cur.kout;
 #pragma unroll
@@ -553,7 +567,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                 const Cell cl = cell_of(p);
                 float val, gu = 0.0f, gv = 0.0f;
                 if ((kin >> k) & 1u) {
-                    taps_plain<TP, GRAD, VJP>(lds_f(tile_cell<TP>(cl, lo, hi, tb - 4u * (TP + 1))), cl.au, cl.av, val,
+                    taps_plain<TP, GRAD, VJP>(lds_f(tile_cell<TP>(cl, tb - 4u * (TP + 1))), cl.au, cl.av, val,
                                               gu, gv);
                 } else {
                     const float cf = __builtin_amdgcn_fmed3f(cl.fu, 1.0f, cmax);
@@ -646,9 +660,16 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
         }
     } else if (col_in) {
         float* out = (chunk == 0 ? vol : a.vpart + (long long)(chunk - 1) * a.nx * a.ny * a.nz) + col_off;
+        if (k0 + BZ <= a.nz && ((size_t)out & 15) == 0) {
+            // whole column inside the volume, 16-byte aligned: one vector store per 4 voxels
 #pragma unroll
-        for (int k = 0; k < BZ; ++k)
-            if (k0 + k < a.nz) out[k] = acc[k];
+            for (int k4 = 0; k4 < BZ / 4; ++k4)
+                ((float4*)out)[k4] = make_float4(acc[4 * k4], acc[4 * k4 + 1], acc[4 * k4 + 2], acc[4 * k4 + 3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < BZ; ++k)
+                if (k0 + k < a.nz) out[k] = acc[k];
+        }
     }
 }
 
@@ -661,10 +682,10 @@ struct BpShared {
 };
 
 // Workgroups per CU the register budget is sized for. Small and middle tiles leave the
-// occupancy to the registers: 6 for the VJP (80 VGPRs; 7 would spill), 8 for the forward (60
-// VGPRs with samples read in groups of 4), the hardware's 32 waves per CU; the largest tile
-// (34 KB) fits four times.
-constexpr int bp_occupancy(int plane, bool vjp) { return plane <= 80 * 36 ? (vjp ? 6 : 8) : (plane <= 128 * 64 ? 4 : 1); }
+// occupancy to the registers: 4 for the VJP (about 110 VGPRs with 16 seeds; at 5 it spills,
+// and spilling costs more than the fifth workgroup gains), 7 for the forward (70 VGPRs with 16
+// accumulators and samples read in groups of 4); the largest tile (49 KB) fits three times.
+constexpr int bp_occupancy(int plane, bool vjp) { return plane <= 80 * 64 ? (vjp ? 4 : 7) : (plane <= 128 * 96 ? 3 : 1); }
 
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
 __global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH, VJP))

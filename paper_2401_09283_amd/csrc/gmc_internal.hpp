@@ -10,11 +10,12 @@
 namespace gmc {
 
 // Voxel bricks are BXY x BXY columns of BRICK_Z voxels; one workgroup of BXY*BXY threads
-// owns a brick and each thread owns one column (a run of BRICK_Z voxels along z). Shallow
-// bricks keep the detector tile small: the tile the brick projects to is staged in LDS once
-// per view, and a small tile leaves the workgroups per CU to the register budget.
+// owns a brick and each thread owns one column (a run of BRICK_Z voxels along z). The tile the
+// brick projects to is staged in LDS once per view: 16 voxels per column share each tile and
+// the per-view work of a column (set-up, reciprocal, VJP wave reduction) over twice the
+// samples of 8, at the price of registers (16 accumulators or seeds per thread).
 constexpr int BXY = 16;
-constexpr int BRICK_Z = 8;
+constexpr int BRICK_Z = 16;
 constexpr int THREADS = BXY * BXY;
 
 // One per (view, brick), 64 bytes, read with scalar loads by the backprojection kernels.
@@ -44,17 +45,17 @@ static_assert(sizeof(BrickDesc) == 64, "descriptor must be 64 bytes");
 constexpr int PART_STRIDE = 16;
 
 // Tile configurations (pitch TP floats, TH rows) compiled into the kernels; one tile per
-// workgroup. 80 x 36 floats plus the border tables take 12.8 KB (the registers, not the 160 KB
-// of LDS, then bound the workgroups per CU); a brick of 16 x 16 x 8 voxels at 1 mm in the
-// 200-degree scan geometry projects to at most about 74 x 38 pixels, and a tile that exceeds
-// the plan's configuration is sampled from global memory instead. 128 x 64 (34.7 KB, four
+// workgroup. 80 x 64 floats plus the border tables take 21 KB (the registers, not the 160 KB
+// of LDS, then bound the workgroups per CU); a brick of 16 x 16 x 16 voxels at 1 mm in the
+// 200-degree scan geometry projects to at most about 73 x 61 pixels, and a tile that exceeds
+// the plan's configuration is sampled from global memory instead. 128 x 96 (49 KB, three
 // workgroups per CU) serves coarse voxels on a fine detector. A row pitch of 80 floats (16
 // banks apart modulo 32) spreads the neighbouring rows a wavefront reads over different LDS
 // banks.
 struct TileCfg {
     int tp, th;
 };
-constexpr TileCfg TILE_CFGS[] = {{40, 40}, {80, 36}, {128, 64}};
+constexpr TileCfg TILE_CFGS[] = {{40, 64}, {80, 64}, {128, 96}};
 constexpr int N_TILE_CFGS = 3;
 
 constexpr int LOSS_BLOCKS = 4096;   // blocks of the reduction kernels of the losses

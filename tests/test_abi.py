@@ -50,7 +50,7 @@ def test_invalid_geometry_is_rejected(bad):
 
 
 @pytest.mark.parametrize("big", [dict(shape=(1 << 14, 1 << 14, 1 << 13)),              # > 2^40 voxels
-                                 dict(shape=(1 << 13, 1 << 13, 1 << 12)),              # 2^27 bricks
+                                 dict(shape=(1 << 13, 1 << 13, 1 << 13)),              # 2^27 bricks
                                  dict(shape=(1 << 12, 1 << 12, 1 << 10), n_views=1 << 16)])  # 2^34 pairs
 def test_oversized_geometry_is_unsupported(big):
     """Work items are numbered in 32 bits: plans beyond 2^26 bricks or 2^33 (brick, view) pairs
@@ -63,16 +63,16 @@ def test_oversized_geometry_is_unsupported(big):
 def test_plan_bricks_and_workspace():
     p = gmc.Plan(_geom())
     info = p.info()
-    assert info["brick"] == (16, 16, 8)
-    assert info["n_bricks"] == 2 * 2 * 3           # ragged: 20, 18, 17 -> 2, 2 and 3 bricks
-    n, nb = 10, 12
+    assert info["brick"] == (16, 16, 16)
+    assert info["n_bricks"] == 2 * 2 * 2           # ragged: 20, 18, 17 -> 2, 2 and 2 bricks
+    n, nb = 10, 8
     # at least: Phat + dPhat + descriptors (64 B) + partials (64 B) per (view, brick)
     assert p.workspace_bytes >= n * 12 * 8 + n * 72 * 8 + 2 * n * nb * 64
     assert p.workspace_bytes % 256 == 0
 
 
 def test_view_chunks_follow_the_brick_count():
-    # 12 bricks and 10 views: the views of every brick split into as many chunks as there are
+    # 8 bricks and 10 views: the views of every brick split into as many chunks as there are
     # views (forward 8, VJP 10), with room for the forward's seven extra partial volumes
     p = gmc.Plan(_geom())
     assert p.info()["view_chunks"] == (8, 10)
@@ -83,7 +83,7 @@ def test_view_chunks_follow_the_brick_count():
     # a volume that fills the GPU by its bricks alone: 4 forward chunks, 16 VJP chunks
     g = gmc.make_geometry(16, 64, 64, (256, 256, 256), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
     info = gmc.Plan(g).info()
-    assert info["n_bricks"] == 16 * 16 * 32 and info["view_chunks"] == (4, 16)
+    assert info["n_bricks"] == 16 * 16 * 16 and info["view_chunks"] == (4, 16)
     # the forward's partial volumes stay within 4 GiB
     g = gmc.make_geometry(16, 64, 64, (1024, 1024, 1024), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
     assert gmc.Plan(g).info()["view_chunks"] == (2, 16)

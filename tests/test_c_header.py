@@ -55,6 +55,6 @@ def test_c_program_uses_the_abi(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     lines = r.stdout.splitlines()
-    assert lines[0].startswith("brick 16 16 8 bricks 12 ws ")
+    assert lines[0].startswith("brick 16 16 16 bricks 8 ws ")
     assert lines[1].startswith("null args -> %d (workspace is NULL" % -2)   # the workspace is checked first
     assert lines[2].startswith("empty geometry -> %d" % -1)

@@ -138,8 +138,18 @@ def test_fullsize_determinism(c1, c1_dev):
     assert torch.equal(g1, g2)
 
 
+def _sumsq64(vol):
+    """The sum-of-squared-differences loss of a GPU volume, summed in FP64 (torch)."""
+    v = vol.double()
+    return float(((v[1:] - v[:-1]) ** 2).sum() + ((v[:, 1:] - v[:, :-1]) ** 2).sum()
+                 + ((v[:, :, 1:] - v[:, :, :-1]) ** 2).sum())
+
+
 def _loss_fn(bp, proj, n_nodes, n_views):
-    """sum-of-squared-differences loss of the volume reconstructed with spline coefficients c"""
+    """sum-of-squared-differences loss of the volume reconstructed with spline coefficients c.
+    The library's loss scalar is an FP32 sum (one ulp is 3e-5 at a loss of 276), which would
+    quantise central differences with steps of 1e-3 to multiples of 0.015; the finite differences therefore take the same loss of the same GPU volume summed in FP64,
+    while the gradient's seed comes from the library's loss kernel."""
     theta = torch.empty((n_views, 6), dtype=torch.float64, device=DEV)
     vol = torch.empty(bp.plan.vol_shape, dtype=torch.float32, device=DEV)
     gvol = torch.empty_like(vol)
@@ -148,13 +158,15 @@ def _loss_fn(bp, proj, n_nodes, n_views):
     def f(c, grad=False):
         gmc.gmc_bspline_theta(n_views, n_nodes, c, theta)
         bp.forward(proj, theta, out=vol)
-        gmc.gmc_loss_sumsq_grad(bp.plan, vol, gvol, loss, bp.workspace)
         if not grad:
-            return float(loss.item())
+            return _sumsq64(vol)
+        gmc.gmc_loss_sumsq_grad(bp.plan, vol, gvol, loss, bp.workspace)
+        L64 = _sumsq64(vol)
+        assert abs(float(loss.item()) - L64) <= 1e-5 * L64   # the FP32 scalar, to its precision
         gt = bp.vjp(proj, theta, gvol)
         gc = torch.empty_like(c)
         gmc.gmc_bspline_grad(n_views, n_nodes, gt, gc)
-        return float(loss.item()), gc.cpu().numpy()
+        return L64, gc.cpu().numpy()
 
     return f
 
@@ -172,7 +184,7 @@ def c1_smooth_proj(c1):
 
 # (gradient mode, data, step in mm or deg, bound on the normwise error, bound on the cosine).
 # The exact mode is the derivative of the forward: the step trades the bilinear kinks it
-# averages over (large steps) against FP32 noise of the loss (small steps); 0.001 is the best
+# averages over (large steps) against FP32 noise of the volume (small steps); 0.001 is the best
 # (about 1 %). The paper's interpolated central differences are not the derivative of the
 # bilinear forward: on ramp-filtered data, rich in content near the pixel Nyquist rate, they
 # deviate from finite differences by about 37 % normwise at every step (cosine 0.93); on

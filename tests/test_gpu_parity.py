@@ -290,6 +290,33 @@ def test_losses_match_oracle(tiny, which):
     assert vol_err(grad.cpu().numpy(), d) <= VOL_TOL
 
 
+@pytest.mark.parametrize("shape", [(5, 3, 1), (7, 6, 5), (9, 4, 10), (3, 17, 7), (16, 16, 18), (1, 1, 4)])
+def test_loss_kernels_on_ragged_shapes_match_oracle(shape):
+    """Both losses on volumes whose z extent leaves 1, 2 or 3 voxels after the runs of four (and
+    single rows, columns and slices): scalars and seeds against the oracle."""
+    from oracle import losses
+
+    rng = np.random.default_rng(sum(shape))
+    vol = rng.uniform(-0.03, 0.08, shape)          # beyond the histogram range on both sides
+    vol_d = _t(vol, torch.float32)
+    vol = vol_d.cpu().numpy().astype(np.float64)   # the values the kernels see
+    plan = gmc.Plan(gmc.make_geometry(4, 16, 16, shape, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0)))
+    ws = plan.new_workspace()
+    grad = torch.empty_like(vol_d)
+    loss = torch.empty(5, dtype=torch.float64, device=DEV)
+    gmc.gmc_loss_entropy_tv(plan, vol_d, 0.3, -0.01, 0.06, 1e-5, grad, loss, ws)
+    L, d, H, T = losses.entropy_tv(vol, 0.3, 64, -0.01, 0.06, 1e-5)
+    lv = loss.cpu().numpy()
+    _report("loss entropy_tv ragged", shape=shape, L=lv[0], ref=L, grad_err=vol_err(grad.cpu().numpy(), d))
+    assert lv[0] == pytest.approx(L, rel=1e-5) and lv[1] == pytest.approx(H, rel=1e-5)
+    assert lv[2] == pytest.approx(T, rel=1e-5)
+    assert vol_err(grad.cpu().numpy(), d) <= VOL_TOL
+    gmc.gmc_loss_sumsq_grad(plan, vol_d, grad, loss[:1], ws)
+    L, d = losses.sumsq_grad(vol)
+    assert loss.cpu().numpy()[0] == pytest.approx(L, rel=1e-5)
+    assert vol_err(grad.cpu().numpy(), d) <= VOL_TOL
+
+
 def test_bspline_and_adam_match_oracle():
     from oracle import motion
 
