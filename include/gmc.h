@@ -78,10 +78,11 @@ typedef struct {
 typedef struct gmc_plan gmc_plan;
 
 /* Create a plan for one geometry. P_nominal (HOST pointer, [n_views][3][4] float64, or
- * NULL) is the static scan; it sizes the on-chip detector tiles (a pair whose tile
- * exceeds them at run time is sampled from global memory instead, with identical
- * results). Host-only; allocates host memory only. GMC_E_UNSUPPORTED beyond 2^26 bricks of
- * 16 x 16 x 16 voxels (about 2.7e11 voxels) or 2^33 (brick, view) pairs. */
+ * NULL) is the static scan; it sizes the on-chip detector tiles and chooses the brick depth
+ * (16 voxels, or 8 where 16 would need the largest tile; 16 without P_nominal). A pair whose
+ * tile exceeds the chosen tile at run time is sampled from global memory instead, with
+ * identical results. Host-only; allocates host memory only. GMC_E_UNSUPPORTED beyond 2^26
+ * bricks of 16 x 16 x 16 voxels (about 2.7e11 voxels) or 2^33 (brick, view) pairs. */
 gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_plan** out);
 gmc_status gmc_plan_destroy(gmc_plan* plan);
 /* Bytes of device workspace every call on this plan needs (256-byte aligned pointer). */
@@ -121,7 +122,7 @@ gmc_status gmc_backproject_vjp(const gmc_plan* plan, const float* proj, const do
  * the stream must belong to the current device). A plan whose VJP needs more returns
  * GMC_E_UNSUPPORTED before anything is launched: about 128 bytes per (brick, view) pair, i.e.
  * up to roughly 5e5 pairs (a 128^3 grid has 512 bricks of 16 x 16 x 16 voxels, so up to about
- * 1000 views). The call allocates nothing (no hipMalloc, no hipFree). geometry_flag (device
+ * 1000 views; half as many with 8-voxel bricks). The call allocates nothing (no hipMalloc, no hipFree). geometry_flag (device
  * int32, or NULL) receives 1 if some (brick, view) pair hit w <= 0 in this call, else 0: this
  * variant's replacement for gmc_check. Every call on one GPU shares that GPU's buffer and
  * leaves its contents there; each call overwrites everything it reads, so no clearing is

@@ -95,20 +95,29 @@ void nominal_tile_extents(const gmc_plan* p, const double* P, std::vector<std::p
     }
 }
 
-// The smallest tile configuration that holds at least 99 % of the nominal tiles with two
-// columns and rows to spare for motion (a smaller LDS tile fits more workgroups per CU; the
-// rest are sampled from global memory).
+// The smallest tile configuration of the plan's brick depth that holds at least 99 % of the
+// nominal tiles with two columns and rows to spare for motion (a smaller LDS tile fits more
+// workgroups per CU; the rest are sampled from global memory); N_TILE_CFGS when none does.
 int choose_tile_cfg(const gmc_plan* p, const double* P) {
     std::vector<std::pair<int, int>> ext;
     nominal_tile_extents(p, P, ext);
     if (ext.empty()) return 0;
+    const TileCfg* cfgs = TILE_CFGS[depth_index(p->bz)];
     for (int c = 0; c < N_TILE_CFGS; ++c) {
         size_t fit = 0;
         for (const auto& e : ext)
-            if (e.first + 2 <= TILE_CFGS[c].tp && e.second + 2 <= TILE_CFGS[c].th) ++fit;
+            if (e.first + 2 <= cfgs[c].tp && e.second + 2 <= cfgs[c].th) ++fit;
         if (fit >= (size_t)(0.99 * (double)ext.size())) return c;
     }
-    return N_TILE_CFGS - 1;
+    return N_TILE_CFGS;
+}
+
+void set_depth(gmc_plan* p, int bz) {
+    p->bz = bz;
+    p->nbx = (p->g.nx + BXY - 1) / BXY;
+    p->nby = (p->g.ny + BXY - 1) / BXY;
+    p->nbz = (p->g.nz + bz - 1) / bz;
+    p->n_bricks = (int)std::min<long long>((long long)p->nbx * p->nby * p->nbz, 1LL << 30);
 }
 
 struct WS {
@@ -232,17 +241,19 @@ gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_p
     gmc_plan* p = new (std::nothrow) gmc_plan();
     if (!p) return fail(GMC_E_INVALID, "out of host memory");
     p->g = *g;
-    p->bz = BRICK_Z;
-    p->nbx = (g->nx + BXY - 1) / BXY;
-    p->nby = (g->ny + BXY - 1) / BXY;
-    p->nbz = (g->nz + p->bz - 1) / p->bz;
-    const long long nb = (long long)p->nbx * p->nby * p->nbz;
     // work items (brick, view chunk) are numbered in 32 bits: at most 2^26 bricks x 16 chunks
-    if (nb > (1LL << 26) || nb * g->n_views > (1LL << 33)) {
-        delete p;
-        return fail(GMC_E_UNSUPPORTED, "too many (brick, view) pairs");
+    {
+        const long long nb = (long long)((g->nx + BXY - 1) / BXY) * ((g->ny + BXY - 1) / BXY) *
+                             ((g->nz + BZ_DEEP - 1) / BZ_DEEP);
+        if (nb > (1LL << 26) || nb * g->n_views > (1LL << 33)) {
+            delete p;
+            return fail(GMC_E_UNSUPPORTED, "too many (brick, view) pairs");
+        }
     }
-    p->n_bricks = (int)nb;
+    // Deep bricks with the middle tile when no nominal geometry is given. With one: deep bricks
+    // if their tiles fit the small or middle configuration, else shallow bricks with the
+    // smallest configuration that holds theirs (the largest when none does).
+    set_depth(p, BZ_DEEP);
     p->tile_cfg = 1;
     if (P_nominal) {
         for (long long e = 0; e < 12LL * g->n_views; ++e)
@@ -251,7 +262,14 @@ gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_p
                 return fail(GMC_E_INVALID, "P_nominal has a non-finite entry");
             }
         p->tile_cfg = choose_tile_cfg(p, P_nominal);
+        const long long nb_shallow = (long long)p->nbx * p->nby * ((g->nz + BZ_SHALLOW - 1) / BZ_SHALLOW);
+        if (p->tile_cfg >= N_TILE_CFGS - 1 && nb_shallow <= (1LL << 26) && nb_shallow * g->n_views <= (1LL << 33)) {
+            set_depth(p, BZ_SHALLOW);
+            p->tile_cfg = choose_tile_cfg(p, P_nominal);
+        }
+        p->tile_cfg = std::min(p->tile_cfg, N_TILE_CFGS - 1);
     }
+    const long long nb = p->n_bricks;
     // Each brick's views are split into chunks, one workgroup per (brick, chunk). The items of
     // a launch are numbered chunk-major and handed to the eight XCDs in contiguous ranges, so
     // with 4 chunks every pair of XCDs gets one chunk of the whole volume, split at its middle
@@ -297,8 +315,8 @@ gmc_status gmc_plan_info(const gmc_plan* plan, int64_t out[8]) {
     out[0] = BXY;
     out[1] = BXY;
     out[2] = plan->bz;
-    out[3] = TILE_CFGS[plan->tile_cfg].tp;
-    out[4] = TILE_CFGS[plan->tile_cfg].th;
+    out[3] = plan_tile(plan).tp;
+    out[4] = plan_tile(plan).th;
     out[5] = plan->n_bricks;
     out[6] = plan->vsplit_fwd;
     out[7] = plan->vsplit_vjp;
@@ -548,7 +566,7 @@ gmc_status gmc_launch_batch(const gmc_work* items, int32_t n_items, void* hip_st
         gmc_status st = gmc_prepare(it.plan, it.P, it.theta, it.phase == 1 ? 1 : 0, it.workspace, hip_stream);
         if (st != GMC_OK) return st;
     }
-    // one launch per (phase, weighting, gradient mode) group and at most MAX_BATCH items
+    // one launch per (phase, weighting, gradient mode, brick depth) group and at most MAX_BATCH items
     std::vector<bool> done(n_items, false);
     for (int32_t q0 = 0; q0 < n_items; ++q0) {
         if (done[q0]) continue;
@@ -560,7 +578,7 @@ gmc_status gmc_launch_batch(const gmc_work* items, int32_t n_items, void* hip_st
         for (int32_t q = q0; q < n_items && tab.n < MAX_BATCH; ++q) {
             const gmc_work& it = items[q];
             if (done[q] || it.phase != lead.phase || it.plan->g.weighting != lead.plan->g.weighting ||
-                it.plan->g.grad_mode != lead.plan->g.grad_mode)
+                it.plan->g.grad_mode != lead.plan->g.grad_mode || it.plan->bz != lead.plan->bz)
                 continue;
             BpArgs ba = bp_args(it.plan, it.proj, carve(it.plan, it.workspace), it.phase == 1);
             // the items of one launch are numbered in 32 bits: a plan that would overflow them
@@ -576,7 +594,8 @@ gmc_status gmc_launch_batch(const gmc_work* items, int32_t n_items, void* hip_st
             done[q] = true;
         }
         tab.per_xcd = (tab.total + 7) / 8;
-        hipError_t e = launch_bp_batch(cfg, lead.plan->g.weighting, lead.plan->g.grad_mode, tab, lead.phase == 1, s);
+        hipError_t e = launch_bp_batch(lead.plan->bz, cfg, lead.plan->g.weighting, lead.plan->g.grad_mode, tab,
+                                       lead.phase == 1, s);
         for (int e2 = 0; e2 < tab.n && e == hipSuccess && lead.phase == 0; ++e2)
             e = launch_sum_chunks(tab.item[e2], s);
         if (e != hipSuccess) return hip_fail(e, "batched backprojection");

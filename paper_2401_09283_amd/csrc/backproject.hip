@@ -682,13 +682,16 @@ struct BpShared {
 };
 
 // Workgroups per CU the register budget is sized for. Small and middle tiles leave the
-// occupancy to the registers: 4 for the VJP (about 110 VGPRs with 16 seeds; at 5 it spills,
-// and spilling costs more than the fifth workgroup gains), 7 for the forward (70 VGPRs with 16
-// accumulators and samples read in groups of 4); the largest tile (49 KB) fits three times.
-constexpr int bp_occupancy(int plane, bool vjp) { return plane <= 80 * 64 ? (vjp ? 4 : 7) : (plane <= 128 * 96 ? 3 : 1); }
+// occupancy to the registers: with deep bricks 4 for the VJP (about 110 VGPRs with 16 seeds; at
+// 5 it spills, and spilling costs more than the fifth workgroup gains) and 7 for the forward
+// (70 VGPRs with 16 accumulators and samples read in groups of 4); with shallow bricks 6 and 8
+// (80 and 60 VGPRs). The largest tiles fit three (128 x 96) and four (128 x 64) times.
+constexpr int bp_occupancy(int plane, int bz, bool vjp) {
+    return bz == BZ_DEEP ? (plane <= 80 * 64 ? (vjp ? 4 : 7) : 3) : (plane <= 80 * 40 ? (vjp ? 6 : 8) : 4);
+}
 
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
-__global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH, VJP))
+__global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH, BZ, VJP))
     k_bp(BpArgs a, const BrickDesc* __restrict__ desc, const float* __restrict__ proj, float* __restrict__ vol,
          const float* __restrict__ gvol, float* __restrict__ part) {
     __shared__ BpShared<TP, TH> sh;
@@ -701,7 +704,7 @@ __global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH, VJP))
 // Several plans in one launch: the work items of all plans form one index space (plan q owns
 // [begin_q, begin_q + n_bricks_q vsplit_q)), mapped to XCDs like a single plan's items.
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
-__global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH, VJP)) k_bp_batch(BatchTable tab) {
+__global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH, BZ, VJP)) k_bp_batch(BatchTable tab) {
     __shared__ BpShared<TP, TH> sh;
     const int blk = blockIdx.x;
     const int g = (blk & 7) * tab.per_xcd + (blk >> 3);
@@ -761,12 +764,19 @@ hipError_t launch_batch_cfg(int W, int G, const BatchTable& tab, bool vjp, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_bp_batch(int tile_cfg, int weighting, int grad_mode, const BatchTable& tab, bool vjp, hipStream_t s) {
+#define GMC_TILE(D, C) TILE_CFGS[D][C].tp, TILE_CFGS[D][C].th, (D == 0 ? BZ_DEEP : BZ_SHALLOW)
+
+hipError_t launch_bp_batch(int bz, int tile_cfg, int weighting, int grad_mode, const BatchTable& tab, bool vjp,
+                           hipStream_t s) {
     if (tab.n < 1 || tab.n > MAX_BATCH || tab.total < 1) return hipErrorInvalidValue;
-    switch (tile_cfg) {
-        case 0: return launch_batch_cfg<TILE_CFGS[0].tp, TILE_CFGS[0].th, BRICK_Z>(weighting, grad_mode, tab, vjp, s);
-        case 1: return launch_batch_cfg<TILE_CFGS[1].tp, TILE_CFGS[1].th, BRICK_Z>(weighting, grad_mode, tab, vjp, s);
-        case 2: return launch_batch_cfg<TILE_CFGS[2].tp, TILE_CFGS[2].th, BRICK_Z>(weighting, grad_mode, tab, vjp, s);
+    if (bz != BZ_DEEP && bz != BZ_SHALLOW) return hipErrorInvalidValue;
+    switch (3 * depth_index(bz) + tile_cfg) {
+        case 0: return launch_batch_cfg<GMC_TILE(0, 0)>(weighting, grad_mode, tab, vjp, s);
+        case 1: return launch_batch_cfg<GMC_TILE(0, 1)>(weighting, grad_mode, tab, vjp, s);
+        case 2: return launch_batch_cfg<GMC_TILE(0, 2)>(weighting, grad_mode, tab, vjp, s);
+        case 3: return launch_batch_cfg<GMC_TILE(1, 0)>(weighting, grad_mode, tab, vjp, s);
+        case 4: return launch_batch_cfg<GMC_TILE(1, 1)>(weighting, grad_mode, tab, vjp, s);
+        case 5: return launch_batch_cfg<GMC_TILE(1, 2)>(weighting, grad_mode, tab, vjp, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -790,11 +800,14 @@ hipError_t launch_sum_chunks(const BpArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_bp(const gmc_plan* p, const BpArgs& a, bool vjp, hipStream_t s) {
-    if (p->bz != BRICK_Z) return hipErrorInvalidValue;
-    switch (p->tile_cfg) {
-        case 0: return launch_cfg<TILE_CFGS[0].tp, TILE_CFGS[0].th, BRICK_Z>(p, a, vjp, s);
-        case 1: return launch_cfg<TILE_CFGS[1].tp, TILE_CFGS[1].th, BRICK_Z>(p, a, vjp, s);
-        case 2: return launch_cfg<TILE_CFGS[2].tp, TILE_CFGS[2].th, BRICK_Z>(p, a, vjp, s);
+    if (p->bz != BZ_DEEP && p->bz != BZ_SHALLOW) return hipErrorInvalidValue;
+    switch (3 * depth_index(p->bz) + p->tile_cfg) {
+        case 0: return launch_cfg<GMC_TILE(0, 0)>(p, a, vjp, s);
+        case 1: return launch_cfg<GMC_TILE(0, 1)>(p, a, vjp, s);
+        case 2: return launch_cfg<GMC_TILE(0, 2)>(p, a, vjp, s);
+        case 3: return launch_cfg<GMC_TILE(1, 0)>(p, a, vjp, s);
+        case 4: return launch_cfg<GMC_TILE(1, 1)>(p, a, vjp, s);
+        case 5: return launch_cfg<GMC_TILE(1, 2)>(p, a, vjp, s);
         default: return hipErrorInvalidValue;
     }
 }

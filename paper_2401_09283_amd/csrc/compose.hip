@@ -202,8 +202,8 @@ hipError_t launch_setup(const gmc_plan* p, const double* Phat, BrickDesc* desc, 
     a.bz = p->bz;
     a.W = p->g.det_w;
     a.H = p->g.det_h;
-    a.tp = TILE_CFGS[p->tile_cfg].tp;
-    a.th_max = TILE_CFGS[p->tile_cfg].th;
+    a.tp = plan_tile(p).tp;
+    a.th_max = plan_tile(p).th;
     a.flags = p->g.flags;
     a.ox = p->g.origin_mm[0];
     a.oy = p->g.origin_mm[1];

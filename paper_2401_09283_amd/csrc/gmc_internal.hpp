@@ -9,13 +9,16 @@
 
 namespace gmc {
 
-// Voxel bricks are BXY x BXY columns of BRICK_Z voxels; one workgroup of BXY*BXY threads
-// owns a brick and each thread owns one column (a run of BRICK_Z voxels along z). The tile the
-// brick projects to is staged in LDS once per view: 16 voxels per column share each tile and
-// the per-view work of a column (set-up, reciprocal, VJP wave reduction) over twice the
-// samples of 8, at the price of registers (16 accumulators or seeds per thread).
+// Voxel bricks are BXY x BXY columns of bz voxels; one workgroup of BXY*BXY threads owns a
+// brick and each thread owns one column (a run of bz voxels along z). The tile the brick
+// projects to is staged in LDS once per view. A plan takes deep bricks (16 voxels) where their
+// tiles fit the small or middle tile configuration: each tile and the per-view work of a
+// column (set-up, reciprocal, VJP wave reduction) then serve twice the samples of 8, at the
+// price of registers (16 accumulators or seeds per thread). Coarse voxels on a fine detector
+// project 16 voxels to taller tiles than the largest configuration holds at full occupancy;
+// such plans take shallow bricks (8 voxels).
 constexpr int BXY = 16;
-constexpr int BRICK_Z = 16;
+constexpr int BZ_DEEP = 16, BZ_SHALLOW = 8;
 constexpr int THREADS = BXY * BXY;
 
 // One per (view, brick), 64 bytes, read with scalar loads by the backprojection kernels.
@@ -44,19 +47,28 @@ static_assert(sizeof(BrickDesc) == 64, "descriptor must be 64 bytes");
 // the tile origin (ou, ov) as int bits, then 2 unused slots.
 constexpr int PART_STRIDE = 16;
 
-// Tile configurations (pitch TP floats, TH rows) compiled into the kernels; one tile per
-// workgroup. 80 x 64 floats plus the border tables take 21 KB (the registers, not the 160 KB
-// of LDS, then bound the workgroups per CU); a brick of 16 x 16 x 16 voxels at 1 mm in the
-// 200-degree scan geometry projects to at most about 73 x 61 pixels, and a tile that exceeds
-// the plan's configuration is sampled from global memory instead. 128 x 96 (49 KB, three
-// workgroups per CU) serves coarse voxels on a fine detector. A row pitch of 80 floats (16
-// banks apart modulo 32) spreads the neighbouring rows a wavefront reads over different LDS
-// banks.
+// Tile configurations (pitch TP floats, TH rows) compiled into the kernels, per brick depth;
+// one tile per workgroup. 80 x 64 floats plus the border tables take 21 KB (the registers, not
+// the 160 KB of LDS, then bound the workgroups per CU); a brick of 16 x 16 x 16 voxels at 1 mm
+// in the 200-degree scan geometry projects to at most about 73 x 61 pixels, and a tile that
+// exceeds the plan's configuration is sampled from global memory instead. 128 x 96 (49 KB,
+// three workgroups per CU) and, for shallow bricks, 128 x 64 (34 KB, four per CU) serve coarse
+// voxels on a fine detector. Within a depth the configurations grow in both extents, so a
+// batched launch can run every plan with the largest configuration among them. A row pitch of
+// 80 floats (16 banks apart modulo 32) spreads the neighbouring rows a wavefront reads over
+// different LDS banks.
 struct TileCfg {
     int tp, th;
 };
-constexpr TileCfg TILE_CFGS[] = {{40, 64}, {80, 64}, {128, 96}};
 constexpr int N_TILE_CFGS = 3;
+constexpr TileCfg TILE_CFGS[2][N_TILE_CFGS] = {{{40, 64}, {80, 64}, {128, 96}},    // deep bricks
+                                               {{40, 40}, {80, 40}, {128, 64}}};   // shallow bricks
+__host__ __device__ constexpr int depth_index(int bz) { return bz == BZ_DEEP ? 0 : 1; }
+static_assert(TILE_CFGS[0][0].tp <= TILE_CFGS[0][1].tp && TILE_CFGS[0][1].tp <= TILE_CFGS[0][2].tp &&
+                  TILE_CFGS[0][0].th <= TILE_CFGS[0][1].th && TILE_CFGS[0][1].th <= TILE_CFGS[0][2].th &&
+                  TILE_CFGS[1][0].tp <= TILE_CFGS[1][1].tp && TILE_CFGS[1][1].tp <= TILE_CFGS[1][2].tp &&
+                  TILE_CFGS[1][0].th <= TILE_CFGS[1][1].th && TILE_CFGS[1][1].th <= TILE_CFGS[1][2].th,
+              "tile configurations grow in both extents");
 
 constexpr int LOSS_BLOCKS = 4096;   // blocks of the reduction kernels of the losses
 constexpr int HIST_BLOCKS = 1024;   // blocks of the histogram kernel (64 KB of LDS each)
@@ -66,15 +78,17 @@ constexpr int HIST_BINS = 64;
 
 struct gmc_plan {
     gmc_geometry g;
-    int bz;                      // brick depth (voxels along z)
+    int bz;                      // brick depth (voxels along z): BZ_DEEP or BZ_SHALLOW
     int nbx, nby, nbz, n_bricks;
-    int tile_cfg;                // index into TILE_CFGS
+    int tile_cfg;                // index into TILE_CFGS[depth_index(bz)]
     int vsplit_fwd, vsplit_vjp;  // view chunks per brick (items = bricks x chunks) of each pass
     // workspace layout (byte offsets)
     size_t off_phat, off_dphat, off_desc, off_part, off_G, off_status, off_loss, off_hist, off_vpart, ws_bytes;
 };
 
 namespace gmc {
+
+inline TileCfg plan_tile(const gmc_plan* p) { return TILE_CFGS[depth_index(p->bz)][p->tile_cfg]; }
 
 struct BpArgs {
     const float* proj;
@@ -102,9 +116,10 @@ hipError_t launch_compose(const double* theta, const double* P, double* Phat, do
                           hipStream_t s);
 hipError_t launch_setup(const gmc_plan* p, const double* Phat, BrickDesc* desc, int* status, hipStream_t s);
 hipError_t launch_bp(const gmc_plan* p, const BpArgs& a, bool vjp, hipStream_t s);
-// one launch over all items of tab; every plan must share weighting and gradient mode, and
-// tile_cfg must be at least each plan's own tile configuration
-hipError_t launch_bp_batch(int tile_cfg, int weighting, int grad_mode, const BatchTable& tab, bool vjp, hipStream_t s);
+// one launch over all items of tab; every plan must share weighting, gradient mode and brick
+// depth bz, and tile_cfg must be at least each plan's own tile configuration
+hipError_t launch_bp_batch(int bz, int tile_cfg, int weighting, int grad_mode, const BatchTable& tab, bool vjp,
+                           hipStream_t s);
 // vol += sum of the chunk partial volumes (fixed order), for a forward run with a.vsplit > 1
 hipError_t launch_sum_chunks(const BpArgs& a, hipStream_t s);
 hipError_t launch_reduce_chain(const gmc_plan* p, const float* part, const double* dPhat, double* G,

@@ -93,10 +93,14 @@ def test_nominal_geometry_picks_the_tile():
     from synth import CONFIGS
     from synth.geometry import projection_matrices
 
-    for name, pitch in (("tiny", 40), ("head256", 80)):
+    # deep bricks where their tiles fit the small or middle tile; the paper's coarse voxels on a
+    # fine detector project 16-voxel bricks taller than the largest tile holds: shallow bricks
+    for name, pitch, rows, bz in (("tiny", 40, 64, 16), ("head256", 80, 64, 16), ("serve384", 80, 64, 16),
+                                  ("paper128", 128, 64, 8)):
         cfg = CONFIGS[name]
         g = gmc.make_geometry(cfg.n_views, cfg.det_w, cfg.det_h, cfg.grid.shape, cfg.grid.voxel_mm, cfg.grid.origin_mm)
-        assert gmc.Plan(g, projection_matrices(cfg.scan)).info()["tile_pitch"] == pitch
+        info = gmc.Plan(g, projection_matrices(cfg.scan)).info()
+        assert (info["tile_pitch"], info["tile_rows"], info["brick"]) == (pitch, rows, (16, 16, bz)), name
 
 
 @pytest.mark.parametrize("geo", [dict(shape=(1 << 23, 2, 2)),                                  # axis > 2^22
