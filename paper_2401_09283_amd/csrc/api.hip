@@ -241,7 +241,7 @@ gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_p
     gmc_plan* p = new (std::nothrow) gmc_plan();
     if (!p) return fail(GMC_E_INVALID, "out of host memory");
     p->g = *g;
-    // work items (brick, view chunk) are numbered in 32 bits: at most 2^26 bricks x 16 chunks
+    // work items (brick, view chunk) are numbered in 32 bits: at most 2^26 bricks (and 2^30 items)
     {
         const long long nb = (long long)((g->nx + BXY - 1) / BXY) * ((g->ny + BXY - 1) / BXY) *
                              ((g->nz + BZ_DEEP - 1) / BZ_DEEP);
@@ -275,16 +275,18 @@ gmc_status gmc_plan_create(const gmc_geometry* g, const double* P_nominal, gmc_p
     // with 4 chunks every pair of XCDs gets one chunk of the whole volume, split at its middle
     // z-slab (bricks near the ends of the cone are cheaper: symmetric halves keep the XCDs
     // equally loaded), and shorter items leave a shorter tail at the end of the launch. The
-    // VJP's partials are per view already: it takes 16 chunks (2 per XCD), whose workgroups
-    // resident on an XCD read the tiles of fewer views at a time (half the L2 misses of 4
-    // chunks). The forward pays one partial volume per extra chunk (capped at 4 GiB) and a
-    // summation: 4 chunks, 8 below 3072 bricks (two rounds of the GPU's workgroup slots).
+    // VJP's partials are per view already: it takes 32 chunks (4 per XCD; at most 2^30 items),
+    // whose workgroups resident on an XCD read the tiles of fewer views at a time (half the L2
+    // misses of 4 chunks), and whose half-wave orientation (chosen per chunk) then suits every
+    // view of its 6-degree chunk. The forward pays one partial volume per extra chunk (capped
+    // at 4 GiB) and a summation: 4 chunks, 8 below 3072 bricks (two rounds of the GPU's
+    // workgroup slots).
     {
         const long long nv = g->n_views;
         const long long vol_bytes = (long long)g->nx * g->ny * g->nz * (long long)sizeof(float);
         const long long fwd = std::min<long long>({nb < 3072 ? 8LL : 4LL, nv, 1 + (4LL << 30) / vol_bytes});
         p->vsplit_fwd = (int)std::max<long long>(1, fwd);
-        p->vsplit_vjp = (int)std::min<long long>(16LL, nv);
+        p->vsplit_vjp = (int)std::min<long long>({32LL, nv, std::max<long long>(1, (1LL << 30) / nb)});
     }
     const size_t n = (size_t)g->n_views;
     size_t off = 0;

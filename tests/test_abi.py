@@ -84,6 +84,12 @@ def test_view_chunks_follow_the_brick_count():
     g = gmc.make_geometry(16, 64, 64, (256, 256, 256), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
     info = gmc.Plan(g).info()
     assert info["n_bricks"] == 16 * 16 * 16 and info["view_chunks"] == (4, 16)
+    # with more views the VJP takes 32 chunks, fewer where 32 would pass 2^30 work items
+    g = gmc.make_geometry(64, 64, 64, (256, 256, 256), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+    assert gmc.Plan(g).info()["view_chunks"] == (4, 32)
+    g = gmc.make_geometry(64, 64, 64, (1 << 13, 1 << 13, 1 << 12), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+    info = gmc.Plan(g).info()
+    assert info["n_bricks"] == 1 << 26 and info["view_chunks"][1] == 16
     # the forward's partial volumes stay within 4 GiB
     g = gmc.make_geometry(16, 64, 64, (1024, 1024, 1024), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
     assert gmc.Plan(g).info()["view_chunks"] == (2, 16)
