@@ -187,10 +187,13 @@ def c1_smooth_proj(c1):
 # averages over (large steps) against FP32 noise of the volume (small steps); 0.001 is the best
 # (about 1 %). The paper's interpolated central differences are not the derivative of the
 # bilinear forward: on ramp-filtered data, rich in content near the pixel Nyquist rate, they
-# deviate from finite differences by about 37 % normwise at every step (cosine 0.93); on
-# smooth data they agree. Both are recorded.
+# deviate from finite differences by 37.7 % normwise (cosine 0.927); on smooth data they agree.
+# The raw-data paper-mode case therefore cannot bound an error; its measured deviation is held
+# as a regression value instead (PAPER_RAW_FD): a gradient a few percent off in scale or
+# direction moves it out of the band. The dense oracle parity tests pin that gradient itself.
 FD_CASES = [("exact", "raw", 1e-3, 3e-2, 0.9995), ("paper", "smooth", 3e-3, 5e-2, 0.999),
-            ("exact", "smooth", 3e-3, 3e-2, 0.9995), ("paper", "raw", 3e-3, 0.45, 0.9)]
+            ("exact", "smooth", 3e-3, 3e-2, 0.9995), ("paper", "raw", 3e-3, None, None)]
+PAPER_RAW_FD = (0.3775, 0.9267)   # (normwise deviation, cosine) measured on MI355X
 
 
 @pytest.mark.parametrize("grad_mode,data,eps,max_rel,min_cos", FD_CASES)
@@ -217,4 +220,7 @@ def test_finite_differences_through_spline_coefficients(c1, c1_dev, c1_smooth_pr
     rel = np.linalg.norm(fd - an) / np.linalg.norm(fd)
     cos = float(np.dot(fd, an) / np.linalg.norm(fd) / np.linalg.norm(an))
     _report("fd 256^3", grad=grad_mode, data=data, eps=eps, normwise=rel, cosine=cos, loss=L0)
-    assert rel <= max_rel and cos >= min_cos
+    if max_rel is None:
+        assert abs(rel - PAPER_RAW_FD[0]) <= 0.01 and abs(cos - PAPER_RAW_FD[1]) <= 0.002
+    else:
+        assert rel <= max_rel and cos >= min_cos
