@@ -334,9 +334,14 @@ template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
 __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __restrict__ desc,
                                          const float* __restrict__ proj, float* __restrict__ vol,
                                          const float* __restrict__ gvol, float* __restrict__ part, const int item,
-                                         float* __restrict__ sT, float2* __restrict__ sCol, float2* __restrict__ sRow,
+                                         float* __restrict__ sT, float* __restrict__ sCol, float* __restrict__ sRow,
                                          float* __restrict__ sRed) {
     constexpr int NSEG = (TP + 63) / 64;
+    // The VJP stores the whole tile; the forward needs no halo and stores rows and columns
+    // 1 .. extent - 2, its row r at buffer row r - 1 (so its buffer has TH - 2 rows). Border
+    // tables hold (z, s) pairs for the VJP and z alone for the forward.
+    constexpr int H0 = VJP ? 0 : 1;
+    constexpr unsigned TBL = VJP ? 8u : 4u;
     static_assert(BZ % FWD_GROUP == 0, "the forward samples a column in whole groups");
     static_assert(BZ % 4 == 0, "seeds and voxels move in groups of 4 along z");
     static_assert(TP <= 128 && 128 + TH <= THREADS, "border tables: columns by threads 0 .. TP-1, rows by 128 ..");
@@ -411,13 +416,11 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
     auto stage = [&](const BrickDesc& D, int vv) {
         if (D.mode != TILE_INTERIOR && D.mode != TILE_EDGE) return;
         const float* __restrict__ img = proj + (long long)vv * a.plane;
-        float* tile = sT;
-        // the VJP needs the whole tile; the forward no halo: rows and columns 1 .. extent - 2
-        constexpr int H0 = VJP ? 0 : 1;
         const int c_end = D.tw - H0, r_end = D.th - H0;
-        // the lane's columns are recomputed per view rather than kept live across the sampling
-        int ln = lane;
-        asm volatile("" : "+v"(ln));
+        // the lane index (and from it the thread index) is recomputed per view with mbcnt rather
+        // than kept live across the sampling
+        const int ln = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+        const int tt = wv * 64 + ln;
 #pragma unroll
         for (int q = 0; q < NSEG; ++q) {
             if (q * 64 >= c_end) break;
@@ -428,27 +431,35 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                     const char* row = (const char*)(img + (long long)(D.ov + H0 + wv) * a.W);
                     const long long step = 16LL * a.W;
                     for (int r = H0 + wv; r < r_end; r += 4, row += step)
-                        __builtin_amdgcn_global_load_lds((const float*)(row + cb), tile + r * TP + q * 64, 4, 0, 0);
+                        __builtin_amdgcn_global_load_lds((const float*)(row + cb), sT + (r - H0) * TP + q * 64, 4, 0, 0);
                 } else {
                     for (int r = H0 + wv; r < r_end; r += 4) {
                         const int gr = min(max(D.ov + r, 0), a.H - 1);
                         const char* row = (const char*)(img + (long long)gr * a.W);
-                        __builtin_amdgcn_global_load_lds((const float*)(row + cb), tile + r * TP + q * 64, 4, 0, 0);
+                        __builtin_amdgcn_global_load_lds((const float*)(row + cb), sT + (r - H0) * TP + q * 64, 4, 0, 0);
                     }
                 }
             }
         }
         if (D.mode == TILE_EDGE) {
-            if (t < TP) {
-                const int gc = D.ou + t;
+            if (tt < TP) {
+                const int gc = D.ou + tt;
                 const float z = ((unsigned)gc < (unsigned)a.W) ? 1.0f : 0.0f;
-                const float sg = (gc == 0 || gc == a.W - 1) ? 2.0f : 1.0f;
-                sCol[t] = make_float2(z, sg);
-            } else if (t >= 128 && t < 128 + TH) {
-                const int gr = D.ov + (t - 128);
+                if (VJP) {
+                    sCol[2 * tt] = z;
+                    sCol[2 * tt + 1] = (gc == 0 || gc == a.W - 1) ? 2.0f : 1.0f;
+                } else {
+                    sCol[tt] = z;
+                }
+            } else if (tt >= 128 && tt < 128 + TH) {
+                const int gr = D.ov + (tt - 128);
                 const float z = ((unsigned)gr < (unsigned)a.H) ? 1.0f : 0.0f;
-                const float sg = (gr == 0 || gr == a.H - 1) ? 2.0f : 1.0f;
-                sRow[t - 128] = make_float2(z, sg);
+                if (VJP) {
+                    sRow[2 * (tt - 128)] = z;
+                    sRow[2 * (tt - 128) + 1] = (gr == 0 || gr == a.H - 1) ? 2.0f : 1.0f;
+                } else {
+                    sRow[tt - 128] = z;
+                }
             }
         }
     };
@@ -484,12 +495,14 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
         col.du = m[2] * dz;
         col.dv = m[6] * dz;
         col.dw = m[10] * dz;
-        const float* tile = sT;
+        // LDS byte address of tile row 0 (for the forward one row before its buffer; no
+        // access lands there)
+        const unsigned tile = lds_addr(sT) - 4u * (unsigned)(H0 * TP);
         const float cmax = (float)(cur.tw - 3), rmax = (float)(cur.th - 3);
 
         if (cur.mode == TILE_INTERIOR) {
             // cell (r, c) with 1 <= r <= rmax, 1 <= c <= cmax: every tap, halo included, in the tile
-            const unsigned base = lds_base(tile, 4u);
+            const unsigned base = tile - 4u * 0x4B000000u;
             if (!VJP) {
                 // per group of FWD_GROUP samples: positions first, then all LDS reads, then the
                 // arithmetic, so that the reads of a group are in flight together
@@ -551,7 +564,7 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
         } else if (cur.mode == TILE_EDGE) {
             // per slice k (uniform branches): skip slices that miss the detector, plain taps for
             // slices inside it, masked taps for the slices across its border
-            const unsigned tb = lds_base(tile, 4u), cb = lds_base(sCol, 8u), rb = lds_base(sRow, 8u);
+            const unsigned tb = tile - 4u * 0x4B000000u, cb = lds_base(sCol, TBL), rb = lds_base(sRow, TBL);
             const unsigned kin = cur.kin, kout = cur.kout;
 #pragma unroll
             for (int k = 0; k < BZ; ++k) {
@@ -572,11 +585,22 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
                 } else {
                     const float cf = __builtin_amdgcn_fmed3f(cl.fu, 1.0f, cmax);
                     const float rf = __builtin_amdgcn_fmed3f(cl.fv, 1.0f, rmax);
-                    // border tables: (z, s) pairs of columns cf, cf + 1 and rows rf, rf + 1
-                    LdsF* ct = lds_f(lds_index(cb, 8u, cf));
-                    LdsF* rt = lds_f(lds_index(rb, 8u, rf));
-                    const float2 c0 = make_float2(ct[0], ct[1]), c1 = make_float2(ct[2], ct[3]);
-                    const float2 r0 = make_float2(rt[0], rt[1]), r1 = make_float2(rt[2], rt[3]);
+                    // border tables: (z, s) of columns cf, cf + 1 and rows rf, rf + 1 (the
+                    // forward's tables hold z only; s is not used without gradients)
+                    LdsF* ct = lds_f(lds_index(cb, TBL, cf));
+                    LdsF* rt = lds_f(lds_index(rb, TBL, rf));
+                    float2 c0, c1, r0, r1;
+                    if (VJP) {
+                        c0 = make_float2(ct[0], ct[1]);
+                        c1 = make_float2(ct[2], ct[3]);
+                        r0 = make_float2(rt[0], rt[1]);
+                        r1 = make_float2(rt[2], rt[3]);
+                    } else {
+                        c0 = make_float2(ct[0], 1.0f);
+                        c1 = make_float2(ct[1], 1.0f);
+                        r0 = make_float2(rt[0], 1.0f);
+                        r1 = make_float2(rt[1], 1.0f);
+                    }
                     taps_masked<TP, GRAD, VJP>(lds_f(lds_index(tb, 4u, fmaf(rf, (float)TP, cf))), cl.au, cl.av, c0, c1,
                                                r0, r1, val, gu, gv);
                 }
@@ -673,39 +697,54 @@ __device__ __forceinline__ void bp_brick(const BpArgs& a, const BrickDesc* __res
     }
 }
 
+template <int TP, int TH, bool VJP>
+struct BpShared;
 template <int TP, int TH>
-struct BpShared {
+struct BpShared<TP, TH, true> {
     float sT[TP * TH];
-    float2 sCol[TP];
-    float2 sRow[TH];
+    float sCol[2 * TP];   // (z, s) per tile column
+    float sRow[2 * TH];   // (z, s) per tile row
     float sRed[2 * 4 * 12];
+    __device__ float* red() { return sRed; }
+};
+template <int TP, int TH>
+struct BpShared<TP, TH, false> {
+    float sT[TP * (TH - 2)];   // tile rows 1 .. TH - 2
+    float sCol[TP];            // z per tile column
+    float sRow[TH];            // z per tile row
+    __device__ float* red() { return nullptr; }
 };
 
-// Workgroups per CU the register budget is sized for. Small and middle tiles leave the
-// occupancy to the registers: with deep bricks 4 for the VJP (about 110 VGPRs with 16 seeds; at
-// 5 it spills, and spilling costs more than the fifth workgroup gains) and 7 for the forward
-// (70 VGPRs with 16 accumulators and samples read in groups of 4); with shallow bricks 6 and 8
-// (80 and 60 VGPRs). The largest tiles fit three (128 x 96) and four (128 x 64) times.
+#ifndef GMC_FWD_DEEP_OCC
+#define GMC_FWD_DEEP_OCC 8
+#endif
+// Workgroups per CU the register budget is sized for. With deep bricks: 4 for the VJP (about
+// 110 VGPRs with 16 seeds; at 5 it spills, and spilling costs more than the fifth workgroup
+// gains); 8 for the forward, whose halo-free 80 x 62 buffer and z-only border tables take
+// 20,416 bytes, so that eight fit in the 160 KB of LDS (64 VGPRs: 16 accumulators and samples
+// read in groups of 4). With shallow bricks 6 and 8 (80 and 60 VGPRs). The largest tiles fit
+// three (128 x 96) and four (VJP, 128 x 64) or five (forward) times.
 constexpr int bp_occupancy(int plane, int bz, bool vjp) {
-    return bz == BZ_DEEP ? (plane <= 80 * 64 ? (vjp ? 4 : 7) : 3) : (plane <= 80 * 40 ? (vjp ? 6 : 8) : 4);
+    return bz == BZ_DEEP ? (plane <= 80 * 64 ? (vjp ? 4 : GMC_FWD_DEEP_OCC) : 3)
+                         : (plane <= 80 * 40 ? (vjp ? 6 : 8) : (vjp ? 4 : 5));
 }
 
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
 __global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH, BZ, VJP))
     k_bp(BpArgs a, const BrickDesc* __restrict__ desc, const float* __restrict__ proj, float* __restrict__ vol,
          const float* __restrict__ gvol, float* __restrict__ part) {
-    __shared__ BpShared<TP, TH> sh;
+    __shared__ BpShared<TP, TH, VJP> sh;
     const int blk = blockIdx.x;
     const int item = (blk & 7) * a.per_xcd + (blk >> 3);
     if (item >= a.n_bricks * a.vsplit) return;
-    bp_brick<TP, TH, BZ, WEIGHT, GRAD, VJP>(a, desc, proj, vol, gvol, part, item, sh.sT, sh.sCol, sh.sRow, sh.sRed);
+    bp_brick<TP, TH, BZ, WEIGHT, GRAD, VJP>(a, desc, proj, vol, gvol, part, item, sh.sT, sh.sCol, sh.sRow, sh.red());
 }
 
 // Several plans in one launch: the work items of all plans form one index space (plan q owns
 // [begin_q, begin_q + n_bricks_q vsplit_q)), mapped to XCDs like a single plan's items.
 template <int TP, int TH, int BZ, int WEIGHT, int GRAD, bool VJP>
 __global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH, BZ, VJP)) k_bp_batch(BatchTable tab) {
-    __shared__ BpShared<TP, TH> sh;
+    __shared__ BpShared<TP, TH, VJP> sh;
     const int blk = blockIdx.x;
     const int g = (blk & 7) * tab.per_xcd + (blk >> 3);
     if (g >= tab.total) return;
@@ -714,7 +753,7 @@ __global__ void __launch_bounds__(THREADS, bp_occupancy(TP * TH, BZ, VJP)) k_bp_
         if (g >= tab.begin[e]) q = e;
     const BpArgs& a = tab.item[q];
     bp_brick<TP, TH, BZ, WEIGHT, GRAD, VJP>(a, a.desc, a.proj, a.vol, a.gvol, a.part, g - tab.begin[q], sh.sT, sh.sCol,
-                                           sh.sRow, sh.sRed);
+                                           sh.sRow, sh.red());
 }
 
 namespace {
