@@ -154,29 +154,34 @@ __device__ void setup_one(const SetupArgs& a, const int v, const int b) {
         // (x, y), so the four corners of a slice bound its projection. A slice whose tap cells
         // (c, c+1) x (r, r+1) all satisfy 1 <= c, c+1 <= W-2, 1 <= r, r+1 <= H-2 needs no border
         // rule (central differences stay inside); a slice whose tap cells all lie outside the
-        // detector contributes nothing (values and differences are 0 there). 1e-3 pixel of margin
-        // covers the FP32 positions of the sampling kernels.
-        const double eps = 1e-3;
+        // detector contributes nothing (values and differences are 0 there). The corners are
+        // evaluated in FP32 with the local matrix the sampling kernels use (tile-relative
+        // positions below 2^8 pixels: about 1e-5 pixel of rounding, and the reciprocal within one
+        // ulp); 1e-3 pixel of margin covers the difference to the kernels' positions, which
+        // follow a Newton chain along the column.
+        const float eps = 1e-3f;
+        const float exf = (float)ext[0], eyf = (float)ext[1], dzf = (float)a.dz;
+        const float ouf = (float)ou, ovf = (float)ov;
         for (int k = 0; k < a.bz && k < 16; ++k) {
-            const double z = o[2] + (double)k * a.dz;
-            double ulo = 1e300, uhi = -1e300, vlo = 1e300, vhi = -1e300;
+            const float qz = (float)k * dzf;
+            float ulo = 3.0e38f, uhi = -3.0e38f, vlo = 3.0e38f, vhi = -3.0e38f;
             bool ok = true;
             for (int c = 0; c < 4; ++c) {
-                const double x = o[0] + ((c & 1) ? ext[0] : 0.0);
-                const double y = o[1] + ((c & 2) ? ext[1] : 0.0);
-                const double w = Ph[8] * x + Ph[9] * y + Ph[10] * z + Ph[11];
-                if (!(w > 0.0)) { ok = false; break; }
-                const double rw = rcp64(w);
-                const double uh = (Ph[0] * x + Ph[1] * y + Ph[2] * z + Ph[3]) * rw;
-                const double vh = (Ph[4] * x + Ph[5] * y + Ph[6] * z + Ph[7]) * rw;
-                ulo = fmin(ulo, uh); uhi = fmax(uhi, uh);
-                vlo = fmin(vlo, vh); vhi = fmax(vhi, vh);
+                const float qx = (c & 1) ? exf : 0.0f, qy = (c & 2) ? eyf : 0.0f;
+                const float w = fmaf(d.m[8], qx, fmaf(d.m[9], qy, fmaf(d.m[10], qz, d.m[11])));
+                if (!(w > 0.0f)) { ok = false; break; }
+                const float rw = __builtin_amdgcn_rcpf(w);
+                const float uh = fmaf(d.m[0], qx, fmaf(d.m[1], qy, fmaf(d.m[2], qz, d.m[3]))) * rw;
+                const float vh = fmaf(d.m[4], qx, fmaf(d.m[5], qy, fmaf(d.m[6], qz, d.m[7]))) * rw;
+                ulo = fminf(ulo, uh); uhi = fmaxf(uhi, uh);
+                vlo = fminf(vlo, vh); vhi = fmaxf(vhi, vh);
             }
             if (!ok) continue;
-            const double c0 = floor(ulo - eps), c1 = floor(uhi + eps) + 1.0;
-            const double r0 = floor(vlo - eps), r1 = floor(vhi + eps) + 1.0;
-            if (c0 >= 1.0 && c1 <= (double)(a.W - 2) && r0 >= 1.0 && r1 <= (double)(a.H - 2)) d.kin |= (uint16_t)(1u << k);
-            if (c1 < 0.0 || c0 > (double)(a.W - 1) || r1 < 0.0 || r0 > (double)(a.H - 1)) d.kout |= (uint16_t)(1u << k);
+            // detector cells: tile-relative cell + tile origin (integer-valued floats, exact)
+            const float c0 = floorf(ulo - eps) + ouf, c1 = floorf(uhi + eps) + 1.0f + ouf;
+            const float r0 = floorf(vlo - eps) + ovf, r1 = floorf(vhi + eps) + 1.0f + ovf;
+            if (c0 >= 1.0f && c1 <= (float)(a.W - 2) && r0 >= 1.0f && r1 <= (float)(a.H - 2)) d.kin |= (uint16_t)(1u << k);
+            if (c1 < 0.0f || c0 > (float)(a.W - 1) || r1 < 0.0f || r0 > (float)(a.H - 1)) d.kout |= (uint16_t)(1u << k);
         }
     }
     a.desc[idx] = d;
