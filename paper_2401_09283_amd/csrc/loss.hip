@@ -26,7 +26,7 @@ __device__ __forceinline__ float block_sum(float v, float* sh) {
     return r;
 }
 
-// uniform cubic B-spline window and its derivative
+// uniform cubic B-spline window
 __device__ __forceinline__ float b3(float s) {
     const float a = fabsf(s);
     if (a < 1.0f) return 2.0f / 3.0f - a * a + 0.5f * a * a * a;
@@ -37,17 +37,6 @@ __device__ __forceinline__ float b3(float s) {
     return 0.0f;
 }
 
-__device__ __forceinline__ float db3(float s) {
-    const float a = fabsf(s);
-    float d = 0.0f;
-    if (a < 1.0f)
-        d = a * (1.5f * a - 2.0f);
-    else if (a < 2.0f) {
-        const float t = 2.0f - a;
-        d = -0.5f * t * t;
-    }
-    return s < 0.0f ? -d : d;
-}
 
 }  // namespace
 
@@ -210,125 +199,100 @@ struct GradArgs {
     float lo, inv_d, eps2, lambda;
 };
 
-// One thread per run of four voxels along z (k = 4 kq .. 4 kq + 3 of column (i, j)); all the
-// loads of a run are issued before the arithmetic. The TV seed of a voxel needs the norms at
-// the voxel and at its three backward neighbours; along z the backward neighbour's norm is the
-// previous voxel's own, so a run forms 13 norms for 4 voxels. Values outside the grid are never
-// read (each load is guarded by the index test that makes its difference count).
-template <typename IDX, bool VEC>
+// Tiles of 8 x 8 columns x 32 voxels along z. A block loads the tile and a one-voxel halo on
+// every side (10 x 10 x 34 values, zero outside the grid) into LDS with loads coalesced along
+// z, then computes the seeds of the tile's voxels from LDS: thread t takes z = t mod 32 and
+// every eighth column of the tile, so that a wavefront's stores cover two columns of 32
+// contiguous voxels. The TV seed of a voxel needs the norms at the voxel and at its three
+// backward neighbours (13 values of the halo box); a difference that leaves the grid counts as
+// 0, as in the definition. Norms come as reciprocal square roots (`v_rsq_f32`, about one ulp).
+// Blocks stride over the tiles.
+constexpr int TVX = 8, TVY = 8, TVZ = 32;
+constexpr int TVBX = TVX + 2, TVBY = TVY + 2, TVBZ = TVZ + 2;
+
 __global__ void __launch_bounds__(256) k_entropy_tv_grad(GradArgs a) {
-    __shared__ float coef[HIST_BINS];
+    // coef[3 + b] = dH/dh_b for the 64 bins, 0 for the three bins on either side (the window of
+    // a value in (-3, 65) bin widths reaches bins -3 .. 66; bins outside the range hold nothing)
+    __shared__ float coef[HIST_BINS + 6];
     __shared__ float sh[256];
-    if (threadIdx.x < HIST_BINS) coef[threadIdx.x] = a.hist[HIST_BINS + threadIdx.x];
-    __syncthreads();
+    __shared__ float box[TVBX * TVBY * TVBZ];
+    const int t = threadIdx.x;
+    if (t < HIST_BINS + 6) coef[t] = (t >= 3 && t < HIST_BINS + 3) ? a.hist[HIST_BINS + t - 3] : 0.0f;
     const float* __restrict__ I = a.I;
     float* __restrict__ G = a.grad;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const long long sx = (long long)ny * nz, sy = nz;
-    const IDX nzq = (IDX)((nz + 3) / 4);
-    const IDX nq = (IDX)nx * (IDX)ny * nzq;
+    const long long sx = (long long)ny * nz;
+    const int ntx = (nx + TVX - 1) / TVX, nty = (ny + TVY - 1) / TVY, ntz = (nz + TVZ - 1) / TVZ;
+    const long long n_tiles = (long long)ntx * nty * ntz;
+    auto S = [&](int xl, int yl, int zl) { return box[(xl * TVBY + yl) * TVBZ + zl]; };
     float tv = 0.0f, gh2 = 0.0f, gt2 = 0.0f;
-    for (IDX q = (IDX)blockIdx.x * 256 + threadIdx.x; q < nq; q += (IDX)gridDim.x * 256) {
-        const IDX col = q / nzq;
-        const int k = 4 * (int)(q - col * nzq);
-        const int i = (int)(col / (IDX)ny), j = (int)(col - (IDX)i * (IDX)ny);
-        const long long base = (long long)col * nz + k;
-        const bool xp = i + 1 < nx, yp = j + 1 < ny, xm = i > 0, ym = j > 0, zm = k > 0;
-        // columns, index m = voxel k + m (m = -1 .. 4 where used)
-        float C[6], XP[5], YP[5], XM[5], YM[5], XMYP[4], XPYM[4];
-        if (VEC) {
-            // nz % 4 == 0 and a 16-byte aligned volume: every run is four aligned floats
-            const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            auto run = [&](long long off, bool ok) { return ok ? *(const float4*)(I + off) : z4; };
-            const float4 c4 = run(base, true), xp4 = run(base + sx, xp), yp4 = run(base + sy, yp);
-            const float4 xm4 = run(base - sx, xm), ym4 = run(base - sy, ym);
-            const float4 xmyp4 = run(base - sx + sy, xm && yp), xpym4 = run(base + sx - sy, xp && ym);
-            const bool z4p = k + 4 < nz;
-            C[0] = zm ? I[base - 1] : 0.0f;
-            C[1] = c4.x; C[2] = c4.y; C[3] = c4.z; C[4] = c4.w;
-            C[5] = z4p ? I[base + 4] : 0.0f;
-            XP[0] = (zm && xp) ? I[base + sx - 1] : 0.0f;
-            XP[1] = xp4.x; XP[2] = xp4.y; XP[3] = xp4.z; XP[4] = xp4.w;
-            YP[0] = (zm && yp) ? I[base + sy - 1] : 0.0f;
-            YP[1] = yp4.x; YP[2] = yp4.y; YP[3] = yp4.z; YP[4] = yp4.w;
-            XM[0] = xm4.x; XM[1] = xm4.y; XM[2] = xm4.z; XM[3] = xm4.w;
-            XM[4] = (z4p && xm) ? I[base - sx + 4] : 0.0f;
-            YM[0] = ym4.x; YM[1] = ym4.y; YM[2] = ym4.z; YM[3] = ym4.w;
-            YM[4] = (z4p && ym) ? I[base - sy + 4] : 0.0f;
-            XMYP[0] = xmyp4.x; XMYP[1] = xmyp4.y; XMYP[2] = xmyp4.z; XMYP[3] = xmyp4.w;
-            XPYM[0] = xpym4.x; XPYM[1] = xpym4.y; XPYM[2] = xpym4.z; XPYM[3] = xpym4.w;
-        } else {
-#pragma unroll
-        for (int m = -1; m <= 4; ++m) {
-            const bool in = k + m < nz && (m >= 0 || zm);
-            C[m + 1] = in ? I[base + m] : 0.0f;
-            if (m <= 3) {
-                XP[m + 1] = (in && xp) ? I[base + sx + m] : 0.0f;
-                YP[m + 1] = (in && yp) ? I[base + sy + m] : 0.0f;
-            }
-            if (m >= 0) {
-                XM[m] = (in && xm) ? I[base - sx + m] : 0.0f;
-                YM[m] = (in && ym) ? I[base - sy + m] : 0.0f;
-                if (m <= 3) {
-                    XMYP[m] = (in && xm && yp) ? I[base - sx + sy + m] : 0.0f;
-                    XPYM[m] = (in && xp && ym) ? I[base + sx - sy + m] : 0.0f;
-                }
-            }
+    for (long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int tz = (int)(tile % ntz);
+        const long long txy = tile / ntz;
+        const int ty = (int)(txy % nty), tx = (int)(txy / nty);
+        const int i0 = tx * TVX, j0 = ty * TVY, k0 = tz * TVZ;
+        __syncthreads();   // the previous tile's reads of box are done (and coef is in place)
+        for (int e = t; e < TVBX * TVBY * TVBZ; e += 256) {
+            const int zl = e % TVBZ, xy = e / TVBZ;
+            const int yl = xy % TVBY, xl = xy / TVBY;
+            const int i = i0 - 1 + xl, j = j0 - 1 + yl, k = k0 - 1 + zl;
+            const bool in = (unsigned)i < (unsigned)nx && (unsigned)j < (unsigned)ny && (unsigned)k < (unsigned)nz;
+            box[e] = in ? I[(long long)i * sx + (long long)j * nz + k] : 0.0f;
         }
-        }
-        // own norm of voxel k - 1 (the z-neighbour of voxel k)
-        float prev_n = 1.0f, prev_dz = 0.0f;
-        if (zm) {
-            const float c = C[0];
-            const float dxv = xp ? XP[0] - c : 0.0f, dyv = yp ? YP[0] - c : 0.0f, dzv = C[1] - c;
-            prev_n = sqrtf(fmaf(dxv, dxv, fmaf(dyv, dyv, fmaf(dzv, dzv, a.eps2))));
-            prev_dz = dzv;
-        }
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int kk = k + m;
-            if (kk >= nz) break;
-            const float c = C[m + 1];
-            // entropy seed
-            const float s = (c - a.lo) * a.inv_d - 0.5f;
-            const float fb = floorf(s);
+        __syncthreads();
+        const int zl = (t & 31) + 1, k = k0 + (t & 31);
+        if (k >= nz) continue;
+        const bool zp = k + 1 < nz, zm = k > 0;
+#pragma unroll 2
+        for (int cidx = t >> 5; cidx < TVX * TVY; cidx += 8) {
+            const int xl = (cidx >> 3) + 1, yl = (cidx & 7) + 1;
+            const int i = i0 + xl - 1, j = j0 + yl - 1;
+            if (i >= nx || j >= ny) continue;
+            const bool xp = i + 1 < nx, yp = j + 1 < ny, xm = i > 0, ym = j > 0;
+            const float c = S(xl, yl, zl);
+            // entropy seed: the window's derivative at the four bins b0 - 1 .. b0 + 2 around
+            // the value, as polynomials in its fraction f (those of db3 at f + 1, f, f - 1, f - 2)
+            const float sv = (c - a.lo) * a.inv_d - 0.5f;
+            const float fb = floorf(sv);
             float gh = 0.0f;
             if (fb > -3.0f && fb < (float)HIST_BINS + 1.0f) {
-                const int b0 = (int)fb;
-#pragma unroll
-                for (int o = -1; o <= 2; ++o) {
-                    const int b = b0 + o;
-                    if (b >= 0 && b < HIST_BINS) gh = fmaf(coef[b], db3(s - (float)b), gh);
-                }
+                const int b0 = (int)fb + 3;
+                const float f = sv - fb, g = 1.0f - f;
+                gh = fmaf(coef[b0 - 1], -0.5f * g * g, fmaf(coef[b0], f * fmaf(1.5f, f, -2.0f),
+                          fmaf(coef[b0 + 1], -g * fmaf(1.5f, g, -2.0f), coef[b0 + 2] * (0.5f * f * f))));
             }
             gh *= a.inv_d;
             // TV seed: own term and the terms at the three backward neighbours
-            const bool zp = kk + 1 < nz;
-            const float dx0 = xp ? XP[m + 1] - c : 0.0f, dy0 = yp ? YP[m + 1] - c : 0.0f;
-            const float dz0 = zp ? C[m + 2] - c : 0.0f;
-            const float n0 = sqrtf(fmaf(dx0, dx0, fmaf(dy0, dy0, fmaf(dz0, dz0, a.eps2))));
-            float gt = -(dx0 + dy0 + dz0) / n0;
-            if (xm) {   // norm at (i-1, j, kk)
-                const float p = c - XM[m], qq = yp ? XMYP[m] - XM[m] : 0.0f, r = zp ? XM[m + 1] - XM[m] : 0.0f;
-                gt += p / sqrtf(fmaf(p, p, fmaf(qq, qq, fmaf(r, r, a.eps2))));
+            const float dx0 = xp ? S(xl + 1, yl, zl) - c : 0.0f, dy0 = yp ? S(xl, yl + 1, zl) - c : 0.0f;
+            const float dz0 = zp ? S(xl, yl, zl + 1) - c : 0.0f;
+            const float s0 = fmaf(dx0, dx0, fmaf(dy0, dy0, fmaf(dz0, dz0, a.eps2)));
+            const float rn0 = __builtin_amdgcn_rsqf(s0), n0 = s0 * rn0;
+            float gt = -(dx0 + dy0 + dz0) * rn0;
+            if (xm) {   // norm at (i-1, j, k)
+                const float m = S(xl - 1, yl, zl);
+                const float p = c - m, q = yp ? S(xl - 1, yl + 1, zl) - m : 0.0f, r = zp ? S(xl - 1, yl, zl + 1) - m : 0.0f;
+                gt = fmaf(p, __builtin_amdgcn_rsqf(fmaf(p, p, fmaf(q, q, fmaf(r, r, a.eps2)))), gt);
             }
-            if (ym) {   // norm at (i, j-1, kk)
-                const float p = xp ? XPYM[m] - YM[m] : 0.0f, qq = c - YM[m], r = zp ? YM[m + 1] - YM[m] : 0.0f;
-                gt += qq / sqrtf(fmaf(p, p, fmaf(qq, qq, fmaf(r, r, a.eps2))));
+            if (ym) {   // norm at (i, j-1, k)
+                const float m = S(xl, yl - 1, zl);
+                const float p = xp ? S(xl + 1, yl - 1, zl) - m : 0.0f, q = c - m, r = zp ? S(xl, yl - 1, zl + 1) - m : 0.0f;
+                gt = fmaf(q, __builtin_amdgcn_rsqf(fmaf(p, p, fmaf(q, q, fmaf(r, r, a.eps2)))), gt);
             }
-            if (kk > 0) gt += prev_dz / prev_n;   // norm at (i, j, kk-1)
-            G[base + m] = fmaf(a.lambda, gt, gh);
+            if (zm) {   // norm at (i, j, k-1)
+                const float m = S(xl, yl, zl - 1);
+                const float p = xp ? S(xl + 1, yl, zl - 1) - m : 0.0f, q = yp ? S(xl, yl + 1, zl - 1) - m : 0.0f, r = c - m;
+                gt = fmaf(r, __builtin_amdgcn_rsqf(fmaf(p, p, fmaf(q, q, fmaf(r, r, a.eps2)))), gt);
+            }
+            G[(long long)i * sx + (long long)j * nz + k] = fmaf(a.lambda, gt, gh);
             tv += n0;
             gh2 = fmaf(gh, gh, gh2);
             gt2 = fmaf(gt, gt, gt2);
-            prev_n = n0;
-            prev_dz = dz0;
         }
     }
     const float b0 = block_sum(tv, sh);
     const float b1 = block_sum(gh2, sh);
     const float b2 = block_sum(gt2, sh);
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         a.part[blockIdx.x] = b0;
         a.part[gridDim.x + blockIdx.x] = b1;
         a.part[2 * gridDim.x + blockIdx.x] = b2;
@@ -373,19 +337,7 @@ hipError_t launch_loss_entropy_tv(const gmc_plan* p, const float* vol, double la
     ga.inv_d = inv_d;
     ga.eps2 = (float)(eps * eps);
     ga.lambda = (float)lambda;
-    const long long n_runs = (long long)p->g.nx * p->g.ny * ((p->g.nz + 3) / 4);
-    const bool vec = p->g.nz % 4 == 0 && ((size_t)vol & 15) == 0;
-    if (n_runs < (1LL << 31)) {
-        if (vec)
-            k_entropy_tv_grad<unsigned, true><<<LOSS_BLOCKS, 256, 0, s>>>(ga);
-        else
-            k_entropy_tv_grad<unsigned, false><<<LOSS_BLOCKS, 256, 0, s>>>(ga);
-    } else {
-        if (vec)
-            k_entropy_tv_grad<unsigned long long, true><<<LOSS_BLOCKS, 256, 0, s>>>(ga);
-        else
-            k_entropy_tv_grad<unsigned long long, false><<<LOSS_BLOCKS, 256, 0, s>>>(ga);
-    }
+    k_entropy_tv_grad<<<LOSS_BLOCKS, 256, 0, s>>>(ga);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     float* sums = scratch + 3 * LOSS_BLOCKS;
     k_sum_cols<<<1, 256, 0, s>>>(scratch, LOSS_BLOCKS, 3, sums);
