@@ -71,7 +71,7 @@ static_assert(TILE_CFGS[0][0].tp <= TILE_CFGS[0][1].tp && TILE_CFGS[0][1].tp <= 
               "tile configurations grow in both extents");
 
 constexpr int LOSS_BLOCKS = 4096;   // blocks of the reduction kernels of the losses
-constexpr int HIST_BLOCKS = 1024;   // blocks of the histogram kernel (64 KB of LDS each)
+constexpr int HIST_BLOCKS = 1024;   // blocks of the histogram kernel (32 KB of LDS each)
 constexpr int HIST_BINS = 64;
 
 }  // namespace gmc

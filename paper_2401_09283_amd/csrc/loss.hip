@@ -26,18 +26,6 @@ __device__ __forceinline__ float block_sum(float v, float* sh) {
     return r;
 }
 
-// uniform cubic B-spline window
-__device__ __forceinline__ float b3(float s) {
-    const float a = fabsf(s);
-    if (a < 1.0f) return 2.0f / 3.0f - a * a + 0.5f * a * a * a;
-    if (a < 2.0f) {
-        const float t = 2.0f - a;
-        return t * t * t * (1.0f / 6.0f);
-    }
-    return 0.0f;
-}
-
-
 }  // namespace
 
 // ------------------------------------------------------------------ sum of squared differences
@@ -107,26 +95,40 @@ struct HistArgs {
     float lo, inv_d;
 };
 
-// Per-thread private histograms in LDS ([bin][thread], conflict free), summed per block by a
-// fixed-order tree (thread t of the first 64 sums bin t). Voxels are read four at a time where
-// the volume is 16-byte aligned.
+// Per-thread private histograms in LDS ([bin][thread], conflict free), 128 threads per block
+// so that a block's 64 bins take 32 KB (five blocks per CU) and the bins b and b + 1 of a
+// thread lie 128 words apart, one `ds_read2_b32` / `ds_write2_b32` pair each; summed per block
+// by a fixed-order tree (thread t of the first 64 sums bin t). The window's weights at the four
+// bins b0 - 1 .. b0 + 2 around a value are polynomials in its fraction f. Voxels are read four
+// at a time where the volume is 16-byte aligned.
+constexpr int HIST_THREADS = 128;
+
 __device__ __forceinline__ void hist_add(const HistArgs& a, float* h, int t, float x) {
     const float s = (x - a.lo) * a.inv_d - 0.5f;
     const float fb = floorf(s);
     if (!(fb > -3.0f && fb < (float)HIST_BINS + 1.0f)) return;
     const int b0 = (int)fb;
+    const float f = s - fb, g = 1.0f - f;
+    const float w[4] = {g * g * g * (1.0f / 6.0f), fmaf(f * f, fmaf(0.5f, f, -1.0f), 2.0f / 3.0f),
+                        fmaf(g * g, fmaf(0.5f, g, -1.0f), 2.0f / 3.0f), f * f * f * (1.0f / 6.0f)};
+    if (b0 >= 1 && b0 <= HIST_BINS - 3) {
+        float* p = h + (b0 - 1) * HIST_THREADS + t;
 #pragma unroll
-    for (int o = -1; o <= 2; ++o) {
-        const int b = b0 + o;
-        if (b >= 0 && b < HIST_BINS) h[b * 256 + t] += b3(s - (float)b);
+        for (int o = 0; o < 4; ++o) p[o * HIST_THREADS] += w[o];
+    } else {
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int b = b0 - 1 + o;
+            if (b >= 0 && b < HIST_BINS) h[b * HIST_THREADS + t] += w[o];
+        }
     }
 }
 
-__global__ void __launch_bounds__(256) k_hist(HistArgs a, float* __restrict__ hist_part) {
-    __shared__ float h[HIST_BINS * 256];
+__global__ void __launch_bounds__(HIST_THREADS) k_hist(HistArgs a, float* __restrict__ hist_part) {
+    __shared__ float h[HIST_BINS * HIST_THREADS];
     const int t = threadIdx.x;
-    for (int b = 0; b < HIST_BINS; ++b) h[b * 256 + t] = 0.0f;
-    const long long stride = (long long)gridDim.x * 256, first = (long long)blockIdx.x * 256 + t;
+    for (int b = 0; b < HIST_BINS; ++b) h[b * HIST_THREADS + t] = 0.0f;
+    const long long stride = (long long)gridDim.x * HIST_THREADS, first = (long long)blockIdx.x * HIST_THREADS + t;
     long long done = 0;
     if (((size_t)a.I & 15) == 0) {
         const float4* __restrict__ I4 = (const float4*)a.I;
@@ -142,15 +144,15 @@ __global__ void __launch_bounds__(256) k_hist(HistArgs a, float* __restrict__ hi
     }
     for (long long idx = done + first; idx < a.N; idx += stride) hist_add(a, h, t, a.I[idx]);
     __syncthreads();
-    // pairwise tree over the 256 threads' histograms, all 64 bins at once
-    for (int w = 128; w > 0; w >>= 1) {
-        for (int e = t; e < HIST_BINS * w; e += 256) {
+    // pairwise tree over the block's private histograms, all 64 bins at once
+    for (int w = HIST_THREADS / 2; w > 0; w >>= 1) {
+        for (int e = t; e < HIST_BINS * w; e += HIST_THREADS) {
             const int b = e / w, q = e % w;
-            h[b * 256 + q] += h[b * 256 + q + w];
+            h[b * HIST_THREADS + q] += h[b * HIST_THREADS + q + w];
         }
         __syncthreads();
     }
-    if (t < HIST_BINS) hist_part[(long long)t * gridDim.x + blockIdx.x] = h[t * 256];
+    if (t < HIST_BINS) hist_part[(long long)t * gridDim.x + blockIdx.x] = h[t * HIST_THREADS];
 }
 
 // hist[b] = sum over blocks of the per-block partials (one block per bin, fixed-order tree)
@@ -318,7 +320,7 @@ hipError_t launch_loss_entropy_tv(const gmc_plan* p, const float* vol, double la
     // hist scratch: [64][HIST_BLOCKS] partials, then 129 finals
     float* hist_part = hist;
     float* hist_final = hist + (long long)HIST_BINS * HIST_BLOCKS;
-    k_hist<<<HIST_BLOCKS, 256, 0, s>>>(ha, hist_part);
+    k_hist<<<HIST_BLOCKS, HIST_THREADS, 0, s>>>(ha, hist_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_hist_reduce<<<HIST_BINS, 256, 0, s>>>(hist_part, HIST_BLOCKS, hist_final);
