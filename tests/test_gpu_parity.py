@@ -184,6 +184,36 @@ def test_coarse_voxels_on_a_fine_detector(flags):
         assert np.all(eg <= GRAD_TOL)
 
 
+@pytest.mark.parametrize("pitch_mm,voxel_mm,tile", [(0.6, (0.5, 0.5, 1.5), (40, 40)), (0.4, (0.5, 0.5, 1.0), (80, 40))])
+def test_shallow_bricks_with_the_small_and_middle_tiles(pitch_mm, voxel_mm, tile):
+    """Voxels tall against the pixel pitch: 16-voxel bricks project taller than the middle tile
+    holds, so the plan takes 8-voxel bricks, here with the small and the middle tile (the
+    coarse-voxel case covers the largest); z extent not a multiple of 8, both weightings and
+    gradient modes, the border-table path forced as well. White-noise images for the paper
+    mode, smooth ones for the exact mode (its gradient jumps at pixel borders)."""
+    scan = ScanGeometry(n_views=17, det_w=256, det_h=240, pitch_mm=pitch_mm, arc_deg=200.0)
+    grid = VolumeGrid(40, 36, 43, voxel_mm)
+    rng = np.random.default_rng(43)
+    P = projection_matrices(scan)
+    th = np.concatenate([rng.uniform(-2, 2, (scan.n_views, 3)), rng.uniform(-0.03, 0.03, (scan.n_views, 3))], 1)
+    images = {"paper": rng.standard_normal((scan.n_views, scan.det_h, scan.det_w)).astype(np.float32),
+              "exact": smooth_images(scan, 44)}
+    delta = rng.standard_normal(grid.shape).astype(np.float32)
+    for weighting, grad_mode, flags in (("fdk", "paper", 0), ("paper", "paper", 0), ("fdk", "exact", 0),
+                                        ("paper", "exact", 0), ("fdk", "paper", gmc.FLAG_FORCE_EDGE)):
+        proj = images[grad_mode]
+        s = Setup(scan, grid, P, th, proj, weighting, grad_mode, flags)
+        info = s.bp.plan.info()
+        assert (info["tile_pitch"], info["tile_rows"], info["brick"]) == (tile[0], tile[1], (16, 16, 8))
+        ev = vol_err(s.fwd(), oracle.backproject(s.geo, proj, s.Phat))
+        g, _ = s.vjp(delta)
+        eg = grad_err(g, oracle.chain(oracle.vjp(s.geo, proj, s.Phat, delta), s.dPhat))
+        _report("shallow bricks", tile=tile, weighting=weighting, grad_mode=grad_mode, flags=flags, vol=ev,
+                grad=np.array2string(eg, precision=2))
+        assert ev <= VOL_TOL
+        assert np.all(eg <= GRAD_TOL)
+
+
 def test_oversized_tiles_gather_from_global_memory():
     """A fine detector (0.05 mm pixels): every brick's tile is hundreds of pixels wide, beyond
     every LDS tile and beyond the descriptor's 8-bit extent fields, so all taps come from the

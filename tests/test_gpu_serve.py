@@ -34,8 +34,8 @@ def _items():
     cfg = dataclasses.replace(CONFIGS["serve128"], n_views=60, n=64, voxel_mm=4.0)
     c = make_case(cfg)
     out.append((c.scan, c.grid, c.P, c.theta_true, c.proj))
-    # coarse voxels on a fine detector: this plan takes the largest tile, so the batched launch
-    # runs every item with it
+    # coarse voxels on a fine detector: this plan takes 8-voxel bricks and the largest tile, so
+    # the batched launch splits the items into one group per brick depth
     scan = ScanGeometry(n_views=23, det_w=700, det_h=500, pitch_mm=0.64, arc_deg=360.0)
     grid = VolumeGrid(40, 36, 50, (2.0, 2.0, 2.0))
     th = np.concatenate([rng.uniform(-5, 5, (23, 3)), rng.uniform(-0.08, 0.08, (23, 3))], 1)
