@@ -2,17 +2,17 @@
 //
 // One workgroup of 256 threads owns a brick of 16 x 16 x BZ voxels; thread (li, lj) owns the
 // column of BZ voxels at (li, lj). For every view the workgroup stages the brick's detector
-// tile in LDS (the filtered projection, with a one-pixel halo for the central differences of
-// Sec. II-B.2, which are formed from the tile's taps on the fly), then every thread walks its
-// column: homogeneous position by FMA from the column base, one reciprocal per column and a
-// Newton step per sample, bilinear taps from LDS. A workgroup takes one item: a brick and a
-// contiguous chunk of its views. The forward pass accumulates its BZ voxels in registers over
-// the chunk's views and writes them once (z fastest; chunks after the first into partial
-// volumes that are summed afterwards in chunk order). The VJP keeps the seed of its BZ voxels
-// in registers, sums the per-sample row coefficients of Eq. 4 (6 running sums per thread,
-// since x and y are constant along a column), reduces them over the workgroup with
-// cross-lane permutes at the end of each view and writes one 12-entry partial per
-// (view, brick); k_reduce_chain finishes the sum.
+// tile in LDS (the filtered projection; the VJP's tile has a one-pixel halo for the central
+// differences of Sec. II-B.2, which are formed from the tile's taps on the fly), then every
+// thread walks its column: homogeneous position by FMA from the column base, one reciprocal
+// per column and a Newton step per sample, bilinear taps from LDS. A workgroup takes one
+// item: a brick and a contiguous chunk of its views. The forward pass accumulates its BZ
+// voxels in registers over the chunk's views and writes them once (z fastest; chunks after
+// the first into partial volumes that are summed afterwards in chunk order). The VJP keeps
+// the seed of its BZ voxels in registers, sums the per-sample row coefficients of Eq. 4 (6
+// running sums per thread, since x and y are constant along a column), reduces them over the
+// workgroup with cross-lane permutes at the end of each view and writes one 12-entry partial
+// per (view, brick); k_reduce_chain finishes the sum.
 //
 // Items are numbered chunk-major and each XCD (workgroup id mod 8) takes a contiguous range
 // of them: the workgroups resident on an XCD are neighbouring bricks over the same views,
