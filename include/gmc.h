@@ -119,15 +119,16 @@ gmc_status gmc_backproject_vjp(const gmc_plan* plan, const float* proj, const do
  * the matrices, brick descriptors, per-(view, brick) partials and status word live in a static
  * device buffer of GMC_NOALLOC_SCRATCH_BYTES (64 MiB) that every GPU the library runs on holds
  * until the process ends (set up on the first call on each device, with that device current;
- * the stream must belong to the current device). A plan whose VJP needs more returns
+ * a stream of another device returns GMC_E_INVALID). A plan whose VJP needs more returns
  * GMC_E_UNSUPPORTED before anything is launched: about 128 bytes per (brick, view) pair, i.e.
  * up to roughly 5e5 pairs (a 128^3 grid has 512 bricks of 16 x 16 x 16 voxels, so up to about
- * 1000 views; half as many with 8-voxel bricks). The call allocates nothing (no hipMalloc, no hipFree). geometry_flag (device
- * int32, or NULL) receives 1 if some (brick, view) pair hit w <= 0 in this call, else 0: this
- * variant's replacement for gmc_check. Every call on one GPU shares that GPU's buffer and
- * leaves its contents there; each call overwrites everything it reads, so no clearing is
- * needed between calls, but calls that overlap in time on one GPU (different streams or host
- * threads) race on the buffer and must be serialised by the caller. */
+ * 1000 views; half as many with 8-voxel bricks). The call allocates nothing (no hipMalloc, no
+ * hipFree). geometry_flag (device int32, or NULL) receives 1 if some (brick, view) pair hit
+ * w <= 0 in this call, else 0: this variant's replacement for gmc_check. Every call on one
+ * GPU shares that GPU's buffer and leaves its contents there; each call overwrites everything
+ * it reads, so no clearing is needed between calls, but calls that overlap in time on one GPU
+ * (different streams or host threads) race on the buffer and must be serialised by the
+ * caller. */
 #define GMC_NOALLOC_SCRATCH_BYTES (64u << 20)
 gmc_status gmc_backproject_vjp_noalloc(const gmc_plan* plan, const float* proj, const double* P,
                                        const double* theta, const float* grad_vol, double* grad_theta,

@@ -208,10 +208,18 @@ constexpr int NOALLOC_MAX_DEVICES = 64;
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
 
-gmc_status scratch_of_current_device(void** out) {
+gmc_status scratch_of_current_device(hipStream_t stream, void** out) {
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    // the buffer is the current device's: a stream of another device would run the kernels there
+    if (stream) {
+        hipDevice_t sdev = -1;
+        e = hipStreamGetDevice(stream, &sdev);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamGetDevice");
+        if (sdev != dev)
+            return fail(GMC_E_INVALID, "the stream belongs to device %d but device %d is current", (int)sdev, dev);
+    }
     if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
         return fail(GMC_E_UNSUPPORTED, "device %d: the allocation-free entry point serves devices 0..%d", dev,
                     NOALLOC_MAX_DEVICES - 1);
@@ -405,7 +413,7 @@ gmc_status gmc_backproject_vjp_noalloc(const gmc_plan* plan, const float* proj, 
                     "buffer holds %zu; use gmc_backproject_vjp with a caller workspace",
                     need, plan->n_bricks, plan->g.n_views, (size_t)GMC_NOALLOC_SCRATCH_BYTES);
     void* ws = nullptr;
-    gmc_status st = scratch_of_current_device(&ws);
+    gmc_status st = scratch_of_current_device((hipStream_t)hip_stream, &ws);
     if (st != GMC_OK) return st;
     const hipStream_t s = (hipStream_t)hip_stream;
     const WS w = carve(plan, ws);
